@@ -1,0 +1,338 @@
+"""CPU FP64 oracle for the split pressure-gradient projection step.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or links
+this module: only the test-suite, the smoke check and the CPU-baseline leg of
+the benchmark use it.  It shares no code with the HIP library.
+
+Source: Poblador-Ibanez & Sirignano, "A Volume-of-Fluid method for
+variable-density, two-phase flows at supercritical pressure" (arXiv 2103.01874),
+Section 5.4 (equation numbers count the paper's numbered displays, a
+subequations group counting once):
+
+  * Eq. (27): split of the pressure gradient,
+        (1/rho) grad p^{n+1}  ->  (1/rho0) grad p^{n+1} + (1/rho - 1/rho0) grad p_hat,
+    with p_hat = 2 p^n - p^{n-1} and rho0 = min(rho).
+  * Eq. (28): projection  u^{n+1} = u^p - dt [ grad p/rho0 + (1/rho - 1/rho0) grad p_hat ].
+  * Eq. (29): constant-coefficient PPE
+        lap p = div[(1 - rho0/rho) grad p_hat] + (rho0/dt)(div u^p - div u^{n+1}).
+  * Eq. (25): the variable-coefficient PPE the split replaces (used only by
+    ``solve_variable_coefficient_dense`` to pin the split's exactness claim).
+
+Discretisation (Sec. 5 opening: uniform staggered Cartesian mesh, velocities on
+face centres, scalars at cell centres; Sec. 5.4: standard finite volumes; the
+FFT solver handles periodic or homogeneous-Neumann boundaries):
+
+  Array layout is C order [nz][ny][nx] (x fastest).  x and z are periodic,
+  y is bounded by two walls.
+    u[k][j][i]  : west face of cell i    (nx faces per row, periodic)
+    v[k][j][i]  : south face of cell j   (ny+1 faces; j = 0 and j = ny are walls)
+    w[k][j][i]  : back face of cell k    (nz faces, periodic)
+  D  = cell divergence of face fluxes, G = face gradient of a cell field
+  (zero on wall faces), L = D o G (7-point Laplacian, zero wall flux).
+
+Readings of points the paper leaves open (each is listed in the design notes):
+  * face density rho_f = arithmetic mean of the two adjacent cells, used in both
+    the right-hand side and the projection (the same rho_f in both makes the
+    projected field's divergence exact);
+  * the singular Neumann/periodic problem is made compatible by removing
+    mean(b), and p is fixed by mean(p) = 0;
+  * rho0 <= 0 requests rho0 = min(rho).
+
+Functions follow the paper's order: assemble the right-hand side (Eq. 29),
+solve the Poisson problem, project (Eq. 28).  The spectral solver diagonalises
+L completely (real FFT in x, complex FFT in z, DCT-II in y); the dense solver
+factorises the bordered matrix with LAPACK.  Neither is the GPU's algorithm.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft as sfft
+
+__all__ = [
+    "Grid",
+    "p_hat",
+    "rho0_of",
+    "face_density",
+    "divergence",
+    "gradient",
+    "laplacian",
+    "assemble_rhs",
+    "solve_spectral",
+    "solve_dense",
+    "laplacian_matrix",
+    "correct",
+    "divergence_check",
+    "solve",
+    "ppe_step",
+    "solve_variable_coefficient_dense",
+    "eigenvalues",
+]
+
+
+class Grid:
+    """Uniform staggered grid of nx*ny*nz cells, lengths lx, ly, lz (walls at both y ends)."""
+
+    def __init__(self, nx, ny, nz, lx=2 * np.pi, ly=2.0, lz=2 * np.pi):
+        if min(nx, ny, nz) < 1:
+            raise ValueError("grid sizes must be positive")
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.lx, self.ly, self.lz = float(lx), float(ly), float(lz)
+        self.dx = self.lx / self.nx
+        self.dy = self.ly / self.ny
+        self.dz = self.lz / self.nz
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def vshape(self):
+        return (self.nz, self.ny + 1, self.nx)
+
+    @property
+    def npts(self):
+        return self.nx * self.ny * self.nz
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5.4, Eq. (27): explicit pressure and reference density
+# ---------------------------------------------------------------------------
+
+def p_hat(pn, pnm1):
+    """Linear extrapolation in time p_hat = 2 p^n - p^{n-1} (Eq. 27)."""
+    return 2.0 * np.asarray(pn, dtype=np.float64) - np.asarray(pnm1, dtype=np.float64)
+
+
+def rho0_of(rho, rho0):
+    """rho0 = min(rho) when the caller passes rho0 <= 0 (Eq. 27), else rho0."""
+    return float(np.min(rho)) if rho0 <= 0 else float(rho0)
+
+
+# ---------------------------------------------------------------------------
+# Staggered finite-volume operators (Sec. 5 opening, Sec. 5.4)
+# ---------------------------------------------------------------------------
+
+def face_density(rho):
+    """Density on the three face families: arithmetic mean of the two cells.
+
+    Returns (rx, ry, rz) shaped like (u, v, w).  The wall entries of ry (j = 0
+    and j = ny) carry the adjacent cell's density; they multiply a zero
+    gradient and never enter a result.
+    """
+    rho = np.asarray(rho, dtype=np.float64)
+    rx = 0.5 * (rho + np.roll(rho, 1, axis=2))
+    rz = 0.5 * (rho + np.roll(rho, 1, axis=0))
+    nz, ny, nx = rho.shape
+    ry = np.empty((nz, ny + 1, nx))
+    ry[:, 1:ny, :] = 0.5 * (rho[:, 1:, :] + rho[:, :-1, :])
+    ry[:, 0, :] = rho[:, 0, :]
+    ry[:, ny, :] = rho[:, ny - 1, :]
+    return rx, ry, rz
+
+
+def divergence(g: Grid, u, v, w):
+    """Cell divergence D of face fluxes (u, v, w)."""
+    du = (np.roll(u, -1, axis=2) - u) / g.dx
+    dv = (v[:, 1:, :] - v[:, :-1, :]) / g.dy
+    dw = (np.roll(w, -1, axis=0) - w) / g.dz
+    return du + dv + dw
+
+
+def gradient(g: Grid, p):
+    """Face gradient G of a cell field; zero on the wall faces of y."""
+    p = np.asarray(p, dtype=np.float64)
+    gx = (p - np.roll(p, 1, axis=2)) / g.dx
+    gz = (p - np.roll(p, 1, axis=0)) / g.dz
+    nz, ny, nx = p.shape
+    gy = np.zeros((nz, ny + 1, nx))
+    gy[:, 1:ny, :] = (p[:, 1:, :] - p[:, :-1, :]) / g.dy
+    return gx, gy, gz
+
+
+def laplacian(g: Grid, p):
+    """L p = D(G p): the 7-point Laplacian with zero flux through the walls."""
+    return divergence(g, *gradient(g, p))
+
+
+def eigenvalues(g: Grid):
+    """Closed-form eigenvalues of L on its eigenvectors (modified wavenumbers).
+
+    lam_x(a) = -(4/dx^2) sin^2(pi a / nx)       periodic, a = 0..nx//2
+    lam_y(m) = -(4/dy^2) sin^2(pi m / (2 ny))   Neumann, cos(pi m (j+1/2)/ny)
+    lam_z(c) = -(4/dz^2) sin^2(pi c / nz)       periodic, c = 0..nz-1
+    Returned broadcastable as [nz][ny][nx//2+1].
+    """
+    a = np.arange(g.nx // 2 + 1)
+    m = np.arange(g.ny)
+    c = np.arange(g.nz)
+    lx = -(4.0 / g.dx**2) * np.sin(np.pi * a / g.nx) ** 2
+    ly = -(4.0 / g.dy**2) * np.sin(np.pi * m / (2.0 * g.ny)) ** 2
+    lz = -(4.0 / g.dz**2) * np.sin(np.pi * c / g.nz) ** 2
+    return lz[:, None, None] + ly[None, :, None] + lx[None, None, :]
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5.4, Eq. (29): right-hand side of the constant-coefficient PPE
+# ---------------------------------------------------------------------------
+
+def assemble_rhs(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, S):
+    """b = (rho0/dt)(D u* - S) + D(beta_f G p_hat),  beta_f = 1 - rho0/rho_f."""
+    ph = p_hat(pn, pnm1)
+    rx, ry, rz = face_density(rho)
+    gx, gy, gz = gradient(g, ph)
+    fx = (1.0 - rho0 / rx) * gx
+    fy = (1.0 - rho0 / ry) * gy
+    fz = (1.0 - rho0 / rz) * gz
+    return (rho0 / dt) * (divergence(g, us, vs, ws) - S) + divergence(g, fx, fy, fz)
+
+
+# ---------------------------------------------------------------------------
+# Poisson solve: L p = b - mean(b), mean(p) = 0
+# ---------------------------------------------------------------------------
+
+def solve_spectral(g: Grid, b, workers=None):
+    """Full diagonalisation of L: rfft in x, fft in z, DCT-II in y.
+
+    The (0,0,0) coefficient carries mean(b); setting it to zero both removes
+    the incompatible part of b and imposes mean(p) = 0.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    bh = sfft.rfft(b, axis=2, workers=workers)
+    bh = sfft.fft(bh, axis=0, workers=workers)
+    bh = sfft.dct(bh, type=2, axis=1, workers=workers)
+    lam = eigenvalues(g)
+    lam[0, 0, 0] = 1.0
+    ph = bh / lam
+    ph[0, 0, 0] = 0.0
+    ph = sfft.idct(ph, type=2, axis=1, workers=workers)
+    ph = sfft.ifft(ph, axis=0, workers=workers)
+    return sfft.irfft(ph, n=g.nx, axis=2, workers=workers)
+
+
+def laplacian_matrix(g: Grid):
+    """Dense N x N matrix of L, built by applying L to unit vectors."""
+    n = g.npts
+    A = np.empty((n, n))
+    e = np.zeros(n)
+    for col in range(n):
+        e[col] = 1.0
+        A[:, col] = laplacian(g, e.reshape(g.shape)).ravel()
+        e[col] = 0.0
+    return A
+
+
+def solve_dense(g: Grid, b):
+    """Bordered dense solve [[L, 1], [1^T, 0]] [p; mu] = [b; 0] (tiny grids).
+
+    Row sums of L vanish, so mu = mean(b) and L p = b - mean(b), sum(p) = 0.
+    """
+    n = g.npts
+    if n > 4096:
+        raise ValueError("dense oracle is for tiny grids only")
+    M = np.zeros((n + 1, n + 1))
+    M[:n, :n] = laplacian_matrix(g)
+    M[:n, n] = 1.0
+    M[n, :n] = 1.0
+    rhs = np.zeros(n + 1)
+    rhs[:n] = np.asarray(b, dtype=np.float64).ravel()
+    sol = np.linalg.solve(M, rhs)
+    return sol[:n].reshape(g.shape)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5.4, Eq. (28): projection, and the continuity check it must satisfy
+# ---------------------------------------------------------------------------
+
+def correct(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, p):
+    """u^{n+1} = u* - dt [ G p / rho0 + gamma_f G p_hat ],  gamma_f = 1/rho_f - 1/rho0.
+
+    Wall faces of v are not corrected: they keep v*.
+    """
+    ph = p_hat(pn, pnm1)
+    rx, ry, rz = face_density(rho)
+    px, py, pz = gradient(g, p)
+    hx, hy, hz = gradient(g, ph)
+    u = us - dt * (px / rho0 + (1.0 / rx - 1.0 / rho0) * hx)
+    w = ws - dt * (pz / rho0 + (1.0 / rz - 1.0 / rho0) * hz)
+    v = np.array(vs, dtype=np.float64, copy=True)
+    v[:, 1:-1, :] = vs[:, 1:-1, :] - dt * (
+        py[:, 1:-1, :] / rho0 + (1.0 / ry[:, 1:-1, :] - 1.0 / rho0) * hy[:, 1:-1, :]
+    )
+    return u, v, w
+
+
+def divergence_check(g: Grid, us, vs, ws, S, u, v, w):
+    """Continuity residual of the projected field (Eq. 25's constraint).
+
+    S_c = S + mean(D u* - S) is the compatible target divergence.  Returns
+    dict(div_l2, div_max, div0_l2, rel, compat) with
+    rel = ||D u - S_c||_2 / ||D u* - S_c||_2.
+    """
+    d0 = divergence(g, us, vs, ws) - S
+    compat = float(np.mean(d0))
+    d0c = d0 - compat
+    d = divergence(g, u, v, w) - S - compat
+    l2 = float(np.sqrt(np.sum(d * d)))
+    l20 = float(np.sqrt(np.sum(d0c * d0c)))
+    return {
+        "div_l2": l2,
+        "div_max": float(np.max(np.abs(d))),
+        "div0_l2": l20,
+        "rel": l2 / l20 if l20 > 0 else l2,
+        "compat": compat,
+    }
+
+
+def solve(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, S, method="spectral", workers=None):
+    """Pressure of the split projection: zero-mean p with L p = b - mean(b)."""
+    r0 = rho0_of(rho, rho0)
+    b = assemble_rhs(g, r0, dt, us, vs, ws, rho, pn, pnm1, S)
+    if method == "spectral":
+        p = solve_spectral(g, b, workers=workers)
+    elif method == "dense":
+        p = solve_dense(g, b)
+    else:
+        raise ValueError(method)
+    return p, r0, b
+
+
+def ppe_step(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, S, method="spectral", workers=None):
+    """Whole projection step: assemble, solve, project, check continuity."""
+    p, r0, b = solve(g, rho0, dt, us, vs, ws, rho, pn, pnm1, S, method=method, workers=workers)
+    u, v, w = correct(g, r0, dt, us, vs, ws, rho, pn, pnm1, p)
+    chk = divergence_check(g, us, vs, ws, S, u, v, w)
+    return {"p": p, "u": u, "v": v, "w": w, "rho0": r0, "b": b,
+            "compat_defect": float(np.mean(b)) * dt / r0, **chk}
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5.4, Eq. (25): the variable-coefficient problem the split approximates
+# ---------------------------------------------------------------------------
+
+def solve_variable_coefficient_dense(g: Grid, dt, us, vs, ws, rho, S):
+    """Zero-mean q with D((1/rho_f) G q) = (1/dt)(D u* - S_c) (tiny grids).
+
+    Sec. 5.4 states the split is exact when grad p_hat equals grad p^{n+1};
+    feeding q back as p^n = p^{n-1} = q must therefore return p = q.
+    """
+    n = g.npts
+    if n > 4096:
+        raise ValueError("dense oracle is for tiny grids only")
+    rx, ry, rz = face_density(rho)
+    A = np.empty((n, n))
+    e = np.zeros(n)
+    for col in range(n):
+        e[col] = 1.0
+        gx, gy, gz = gradient(g, e.reshape(g.shape))
+        A[:, col] = divergence(g, gx / rx, gy / ry, gz / rz).ravel()
+        e[col] = 0.0
+    d0 = divergence(g, us, vs, ws) - S
+    rhs_c = (d0 - np.mean(d0)) / dt
+    M = np.zeros((n + 1, n + 1))
+    M[:n, :n] = A
+    M[:n, n] = 1.0
+    M[n, :n] = 1.0
+    rhs = np.zeros(n + 1)
+    rhs[:n] = rhs_c.ravel()
+    return np.linalg.solve(M, rhs)[:n].reshape(g.shape)
