@@ -1,0 +1,161 @@
+/*
+ * ppe.h -- C ABI of the MI355X split pressure-gradient projection library.
+ *
+ * The library computes one projection step of the low-Mach two-phase scheme
+ * of Poblador-Ibanez & Sirignano (arXiv 2103.01874), Sec. 5.4:
+ *
+ *   p_hat = 2 p^n - p^{n-1},  rho0 = min(rho)                          (Eq. 27)
+ *   lap p = div[(1 - rho0/rho) grad p_hat] + (rho0/dt)(div u* - S)     (Eq. 29)
+ *   u^{n+1} = u* - dt [ grad p/rho0 + (1/rho - 1/rho0) grad p_hat ]    (Eq. 28)
+ *
+ * where u* is the predictor velocity (the paper's u^p, Eq. 23) and S the
+ * target divergence div u^{n+1} (Eq. 26).  The Poisson equation is solved
+ * directly (Sec. 5.4: a fast solver built from discrete Fourier transforms):
+ * real FFT in x, complex FFT in z, one tridiagonal system in y per wavenumber
+ * pair, inverse FFTs.  Every step runs in HIP kernels on one GPU.
+ *
+ * Grid and layouts (all fields are C-order float64, x fastest):
+ *   nx*ny*nz cells of size dx = lx/nx, dy = ly/ny, dz = lz/nz; x and z are
+ *   periodic, y is bounded by two walls.
+ *   cell fields rho, p^n, p^{n-1}, S, p : [nz][ny][nx]
+ *   u (west face of cell i)             : [nz][ny][nx]
+ *   v (south face of cell j)            : [nz][ny+1][nx]; rows 0 and ny are
+ *                                         the walls (read as given, never
+ *                                         corrected, zero pressure flux)
+ *   w (back face of cell k)             : [nz][ny][nx]
+ *   D = cell divergence, G = face gradient (zero on walls), L = D o G.
+ *   Face density rho_f = (rho_a + rho_b)/2, the same in the right-hand side
+ *   and in the projection, so div u^{n+1} = S_c to rounding, with
+ *   S_c = S + mean(D u* - S).  The pressure is fixed by mean(p) = 0, and
+ *   mean(b) is removed from the right-hand side (compatibility).
+ *
+ * Ownership: every field pointer is a DEVICE pointer owned by the caller;
+ * the plan owns its workspace, twiddle and eigenvalue tables (allocated in
+ * ppe_plan, freed in ppe_plan_destroy).  Outputs must not alias inputs.
+ *
+ * Streams: every call enqueues work on the plan's stream and returns without
+ * waiting for the device.  Results (fields and ppe_info_t records) are valid
+ * once the stream has been synchronised.
+ *
+ * Errors: problems the host can see (null pointer, bad size, unsupported
+ * FFT length, non-positive dt) return a negative ppe_status_t and enqueue
+ * nothing.  Problems only the device can see (non-finite data, refinement
+ * not converged) are written to the instance's ppe_info_t.status; other
+ * instances of a batch are not affected.
+ *
+ * Thread safety: a plan must not be used from two host threads at once.
+ * Distinct plans (on distinct streams) may run concurrently.
+ */
+#ifndef PPE_H
+#define PPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ppe_plan_s* ppe_plan_t;
+
+typedef enum {
+  PPE_OK = 0,
+  PPE_ERR_ARG = -1,          /* bad argument (null pointer, size, dt <= 0, ...) */
+  PPE_ERR_NOMEM = -2,        /* device allocation failed */
+  PPE_ERR_DEVICE = -3,       /* a HIP call failed */
+  PPE_ERR_NOT_CONVERGED = -4,/* (info only) refinement stopped above tol */
+  PPE_ERR_NONFINITE = -5,    /* (info only) a non-finite value reached the solve */
+  PPE_ERR_UNSUPPORTED = -6   /* FFT length not of the form 2^a 3^b, or too long */
+} ppe_status_t;
+
+/* Precision of the spectral passes (FFTs and tridiagonal sweeps). */
+typedef enum {
+  PPE_PREC_FP64 = 0,   /* FP64 storage and arithmetic: the direct solve */
+  PPE_PREC_MIXED = 1   /* FP32 spectra in memory, FP64 arithmetic in registers,
+                          FP64 residual, zero mode, gauge and refinement */
+} ppe_precision_t;
+
+typedef struct {
+  int32_t nx, ny, nz;      /* cells; nx, nz in 1..2048 of the form 2^a 3^b; 2 <= ny <= 2048 */
+  double lx, ly, lz;       /* domain lengths (> 0) */
+  int32_t precision;       /* ppe_precision_t */
+  double tol;              /* PPE_PREC_MIXED: stop when the relative residual
+                              ||b - mean b - L p||_2 / ||(rho0/dt)(D u* - S_c)||_2
+                              <= tol (the projected field's relative
+                              divergence error); 0 runs max_refine sweeps */
+  int32_t max_refine;      /* PPE_PREC_MIXED: refinement sweeps after the first
+                              solve (>= 0) */
+  int32_t batch;           /* same-shape instances handled per call (>= 1) */
+} ppe_desc_t;
+
+/* Per-instance record, written to DEVICE memory by ppe_solve / ppe_correct. */
+typedef struct {
+  int32_t status;          /* ppe_status_t (PPE_OK, NOT_CONVERGED, NONFINITE) */
+  int32_t iters;           /* refinement sweeps run (0 for PPE_PREC_FP64) */
+  double rho0_used;        /* rho0 actually used */
+  double compat_defect;    /* mean(D u* - S): the incompatible part removed */
+  double res_rel;          /* ppe_solve: last refinement residual (relative);
+                              ppe_correct: div_l2 / div0_l2 */
+  double div_l2;           /* ppe_correct: ||D u^{n+1} - S_c||_2 */
+  double div_max;          /* ppe_correct: max |D u^{n+1} - S_c| */
+  double div0_l2;          /* ||D u* - S_c||_2 */
+  double p_mean;           /* ppe_solve: mean of the returned p (gauge check) */
+} ppe_info_t;
+
+/* Maximum number of instances per call; larger batches need several calls. */
+#define PPE_MAX_BATCH 64
+
+/* Bytes of device memory ppe_plan allocates for this descriptor (workspace,
+ * tables, reduction scratch), for admission control.  0 on a bad descriptor. */
+size_t ppe_plan_workspace_bytes(const ppe_desc_t* desc);
+
+/* Build a plan for `desc` bound to `stream` (a hipStream_t; NULL = the null
+ * stream) on the current device.  Allocates the workspace and FP64 twiddle /
+ * eigenvalue tables.  On success *out holds the plan; on failure *out is NULL. */
+ppe_status_t ppe_plan(const ppe_desc_t* desc, void* stream, ppe_plan_t* out);
+
+/* Release a plan and its device memory (waits for its stream first). */
+ppe_status_t ppe_plan_destroy(ppe_plan_t plan);
+
+/* Re-bind a plan to another stream (same device). */
+ppe_status_t ppe_plan_set_stream(ppe_plan_t plan, void* stream);
+
+/* Pressure solve, Eq. (29) with Eq. (27) (Sec. 5.4).
+ *   rho0[b] : host array; > 0 is used as given, <= 0 requests min(rho) (device)
+ *   dt[b]   : host array, > 0
+ *   us, vs, ws, rho, pn, pnm1, S : host arrays of `batch` device pointers (inputs)
+ *   p       : host array of `batch` device pointers (output, zero-mean)
+ *   info    : device array of `batch` records (output)
+ * For PPE_PREC_MIXED the first solve uses FP32 spectra and is refined with
+ * FP64 residuals until `tol` or `max_refine`. */
+ppe_status_t ppe_solve(ppe_plan_t plan, const double* rho0, const double* dt,
+                       const double* const* us, const double* const* vs, const double* const* ws,
+                       const double* const* rho, const double* const* pn, const double* const* pnm1,
+                       const double* const* S, double* const* p, ppe_info_t* info);
+
+/* Projection, Eq. (28) (Sec. 5.4), and the continuity check of the result.
+ * Reads rho0_used and compat_defect from `info` (as written by ppe_solve for
+ * the same inputs) and writes div_l2, div_max, div0_l2, res_rel and status
+ * (PPE_ERR_NOT_CONVERGED when res_rel > desc.tol > 0).
+ *   u, v, w : host arrays of `batch` device pointers (outputs; the wall rows
+ *             of v are copied from v*). */
+ppe_status_t ppe_correct(ppe_plan_t plan, const double* dt,
+                         const double* const* us, const double* const* vs, const double* const* ws,
+                         const double* const* rho, const double* const* pn, const double* const* pnm1,
+                         const double* const* p, const double* const* S,
+                         double* const* u, double* const* v, double* const* w, ppe_info_t* info);
+
+/* Continuity diagnostic of any staggered field (the constraint behind
+ * Eq. 25): out[3*b + 0] = ||d - mean d||_2, out[3*b + 1] = max |d - mean d|,
+ * out[3*b + 2] = mean d, with d = D u - S.  `out` is a device array. */
+ppe_status_t ppe_residual(ppe_plan_t plan, const double* const* u, const double* const* v,
+                          const double* const* w, const double* const* S, double* out);
+
+/* Library version string (static storage). */
+const char* ppe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPE_H */

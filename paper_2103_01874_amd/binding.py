@@ -1,0 +1,234 @@
+"""Thin ctypes binding of libppe.so (include/ppe.h): argument marshalling only.
+
+Every step of the projection runs in the HIP library.  This module checks
+shapes, dtypes and devices of torch tensors, passes their device pointers
+and the current HIP stream, and decodes the per-instance ``ppe_info_t``
+records.  It fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libppe.so")
+
+PPE_PREC_FP64 = 0
+PPE_PREC_MIXED = 1
+MAX_BATCH = 64
+
+STATUS = {0: "ok", -1: "bad argument", -2: "out of memory", -3: "device error", -4: "not converged",
+          -5: "non-finite", -6: "unsupported"}
+
+
+class PPEError(RuntimeError):
+    pass
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
+                ("batch", ctypes.c_int32)]
+
+
+INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("rho0_used", "<f8"), ("compat_defect", "<f8"),
+                       ("res_rel", "<f8"), ("div_l2", "<f8"), ("div_max", "<f8"), ("div0_l2", "<f8"),
+                       ("p_mean", "<f8")])
+assert INFO_DTYPE.itemsize == 64
+
+EXPORTS = ["ppe_plan_workspace_bytes", "ppe_plan", "ppe_plan_destroy", "ppe_plan_set_stream", "ppe_solve",
+           "ppe_correct", "ppe_residual", "ppe_version"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libppe.so once; raise if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise PPEError(f"{path} is not built; run `python -m paper_2103_01874_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    D = ctypes.POINTER(ctypes.c_double)
+    lib.ppe_plan_workspace_bytes.argtypes = [ctypes.POINTER(Desc)]
+    lib.ppe_plan_workspace_bytes.restype = ctypes.c_size_t
+    lib.ppe_plan.argtypes = [ctypes.POINTER(Desc), P, ctypes.POINTER(P)]
+    lib.ppe_plan.restype = ctypes.c_int
+    lib.ppe_plan_destroy.argtypes = [P]
+    lib.ppe_plan_destroy.restype = ctypes.c_int
+    lib.ppe_plan_set_stream.argtypes = [P, P]
+    lib.ppe_plan_set_stream.restype = ctypes.c_int
+    lib.ppe_solve.argtypes = [P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, P]
+    lib.ppe_solve.restype = ctypes.c_int
+    lib.ppe_correct.argtypes = [P, D, PP, PP, PP, PP, PP, PP, PP, PP, PP, PP, PP, P]
+    lib.ppe_correct.restype = ctypes.c_int
+    lib.ppe_residual.argtypes = [P, PP, PP, PP, PP, P]
+    lib.ppe_residual.restype = ctypes.c_int
+    lib.ppe_version.argtypes = []
+    lib.ppe_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def make_desc(nx, ny, nz, lx=2 * np.pi, ly=2.0, lz=2 * np.pi, precision=PPE_PREC_FP64, tol=1e-12,
+              max_refine=1, batch=1) -> Desc:
+    return Desc(int(nx), int(ny), int(nz), float(lx), float(ly), float(lz), int(precision), float(tol),
+                int(max_refine), int(batch))
+
+
+def workspace_bytes(desc: Desc) -> int:
+    return int(load().ppe_plan_workspace_bytes(ctypes.byref(desc)))
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise PPEError(f"{what} failed: {STATUS.get(st, st)}")
+
+
+def _ptrs(tensors) -> ctypes.Array:
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def _dbl(vals) -> ctypes.Array:
+    arr = (ctypes.c_double * len(vals))()
+    for i, v in enumerate(vals):
+        arr[i] = float(v)
+    return arr
+
+
+def decode_info(info_tensor) -> List[Dict]:
+    """Copy ppe_info_t records (device tensor of float64, 8 per record) to dicts."""
+    raw = info_tensor.detach().cpu().numpy().tobytes()
+    recs = np.frombuffer(raw, dtype=INFO_DTYPE)
+    return [{k: (int(r[k]) if k in ("status", "iters") else float(r[k])) for k in INFO_DTYPE.names} for r in recs]
+
+
+class Plan:
+    """A plan for `batch` same-shape instances, bound to a torch CUDA stream."""
+
+    def __init__(self, nx, ny, nz, lx=2 * np.pi, ly=2.0, lz=2 * np.pi, precision=PPE_PREC_FP64, tol=1e-12,
+                 max_refine=1, batch=1, stream=None, device=None):
+        import torch
+
+        self._torch = torch
+        self.lib = load()
+        self.desc = make_desc(nx, ny, nz, lx, ly, lz, precision, tol, max_refine, batch)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.ppe_plan(ctypes.byref(self.desc), ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(self._h)), "ppe_plan")
+        self.nx, self.ny, self.nz, self.batch = int(nx), int(ny), int(nz), int(batch)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return workspace_bytes(self.desc)
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(self.lib.ppe_plan_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)), "ppe_plan_set_stream")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            self.lib.ppe_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- validation ---------------------------------------------------------
+    def _cell(self, t, name):
+        torch = self._torch
+        shp = (self.nz, self.ny, self.nx)
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device \
+                or tuple(t.shape) != shp or not t.is_contiguous():
+            raise PPEError(f"{name}: expected contiguous float64 {shp} on {self.device}")
+        return t
+
+    def _vface(self, t, name):
+        torch = self._torch
+        shp = (self.nz, self.ny + 1, self.nx)
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device \
+                or tuple(t.shape) != shp or not t.is_contiguous():
+            raise PPEError(f"{name}: expected contiguous float64 {shp} on {self.device}")
+        return t
+
+    def _batch(self, seq, name, v=False):
+        if len(seq) != self.batch:
+            raise PPEError(f"{name}: expected {self.batch} tensors, got {len(seq)}")
+        return [(self._vface if v else self._cell)(t, f"{name}[{i}]") for i, t in enumerate(seq)]
+
+    def new_info(self):
+        return self._torch.zeros(self.batch * 8, dtype=self._torch.float64, device=self.device)
+
+    # -- entry points -------------------------------------------------------
+    def solve(self, rho0: Sequence[float], dt: Sequence[float], us, vs, ws, rho, pn, pnm1, S, p, info=None):
+        """ppe_solve: writes p (list of tensors) and the info records (returned)."""
+        if info is None:
+            info = self.new_info()
+        B = self.batch
+        if len(rho0) != B or len(dt) != B:
+            raise PPEError("rho0 and dt need one value per instance")
+        args = [self._batch(us, "us"), self._batch(vs, "vs", v=True), self._batch(ws, "ws"),
+                self._batch(rho, "rho"), self._batch(pn, "pn"), self._batch(pnm1, "pnm1"), self._batch(S, "S"),
+                self._batch(p, "p")]
+        st = self.lib.ppe_solve(self._h, _dbl(rho0), _dbl(dt), *[_ptrs(a) for a in args],
+                                ctypes.c_void_p(info.data_ptr()))
+        _check(st, "ppe_solve")
+        return info
+
+    def correct(self, dt: Sequence[float], us, vs, ws, rho, pn, pnm1, p, S, u, v, w, info):
+        """ppe_correct: writes u, v, w and the continuity fields of `info`."""
+        args = [self._batch(us, "us"), self._batch(vs, "vs", v=True), self._batch(ws, "ws"),
+                self._batch(rho, "rho"), self._batch(pn, "pn"), self._batch(pnm1, "pnm1"), self._batch(p, "p"),
+                self._batch(S, "S"), self._batch(u, "u"), self._batch(v, "v", v=True), self._batch(w, "w")]
+        st = self.lib.ppe_correct(self._h, _dbl(dt), *[_ptrs(a) for a in args], ctypes.c_void_p(info.data_ptr()))
+        _check(st, "ppe_correct")
+        return info
+
+    def residual(self, u, v, w, S, out=None):
+        """ppe_residual: per instance (||d - mean d||_2, max|d - mean d|, mean d), d = D u - S."""
+        torch = self._torch
+        if out is None:
+            out = torch.zeros(self.batch * 3, dtype=torch.float64, device=self.device)
+        args = [self._batch(u, "u"), self._batch(v, "v", v=True), self._batch(w, "w"), self._batch(S, "S")]
+        st = self.lib.ppe_residual(self._h, *[_ptrs(a) for a in args], ctypes.c_void_p(out.data_ptr()))
+        _check(st, "ppe_residual")
+        return out
+
+
+def to_device(problem, device="cuda"):
+    """Copy a synth.Problem's fields to the device (float64, contiguous)."""
+    import torch
+
+    return {k: torch.from_numpy(np.ascontiguousarray(getattr(problem, k))).to(device)
+            for k in ("us", "vs", "ws", "rho", "pn", "pnm1", "S")}
+
+
+def step(plan: Plan, fields: List[Dict], rho0, dt, outputs: Optional[List[Dict]] = None):
+    """solve + correct for a batch of field dicts; returns (outputs, info tensor)."""
+    torch = plan._torch
+    if outputs is None:
+        outputs = [{"p": torch.empty_like(f["rho"]), "u": torch.empty_like(f["us"]),
+                    "v": torch.empty_like(f["vs"]), "w": torch.empty_like(f["ws"])} for f in fields]
+    g = lambda k: [f[k] for f in fields]
+    o = lambda k: [x[k] for x in outputs]
+    info = plan.solve(rho0, dt, g("us"), g("vs"), g("ws"), g("rho"), g("pn"), g("pnm1"), g("S"), o("p"))
+    plan.correct(dt, g("us"), g("vs"), g("ws"), g("rho"), g("pn"), g("pnm1"), o("p"), g("S"), o("u"), o("v"),
+                 o("w"), info)
+    return outputs, info

@@ -1,0 +1,174 @@
+// hostcheck.cpp -- host-side driver of the kernels' per-thread stage code.
+//
+// TEST SUPPORT ONLY (built into libppe_hostcheck.so, loaded by the CPU test
+// suite, never by the library).  It runs the same __host__ __device__ stage
+// functions the kernels run -- the Stockham FFT stages and the partition-method
+// tridiagonal elimination -- thread by thread on the host, with the read and
+// write halves of each stage separated exactly where the kernels place their
+// barriers.  This checks indexing and algebra without a GPU.
+#include <cstring>
+#include <vector>
+
+#include "ppe_device.hpp"
+#include "ppe_plan_util.hpp"
+
+using namespace ppe;
+
+namespace {
+
+template <int E, int DIR>
+void run_fft(const HostFft& h, const std::vector<double>& tw, cplx<double>* buf) {
+  FftDev f;
+  f.n = h.n;
+  f.e = h.e;
+  f.tc = h.tc;
+  f.nst = h.nst;
+  for (int s = 0; s < kMaxStages; ++s) f.radix[s] = h.radix[s];
+  f.tw = tw.data();
+  int ns = 1;
+  std::vector<cplx<double>> regs((size_t)f.tc * E);
+  for (int s = 0; s < f.nst; ++s) {
+    const int R = f.radix[s];
+    // read half for every thread, then write half for every thread
+    for (int t = 0; t < f.tc; ++t) {
+      cplx<double>* v = &regs[(size_t)t * E];
+      if constexpr (E % 8 == 0) if (R == 8) stage_read<E, 8, double>(buf, 1, t, f, v);
+      if constexpr (E % 4 == 0) if (R == 4) stage_read<E, 4, double>(buf, 1, t, f, v);
+      if constexpr (E % 3 == 0) if (R == 3) stage_read<E, 3, double>(buf, 1, t, f, v);
+      if constexpr (E % 2 == 0) if (R == 2) stage_read<E, 2, double>(buf, 1, t, f, v);
+    }
+    for (int t = 0; t < f.tc; ++t) {
+      cplx<double>* v = &regs[(size_t)t * E];
+      if constexpr (E % 8 == 0) if (R == 8) stage_write<E, 8, DIR, double>(buf, 1, t, ns, f, v);
+      if constexpr (E % 4 == 0) if (R == 4) stage_write<E, 4, DIR, double>(buf, 1, t, ns, f, v);
+      if constexpr (E % 3 == 0) if (R == 3) stage_write<E, 3, DIR, double>(buf, 1, t, ns, f, v);
+      if constexpr (E % 2 == 0) if (R == 2) stage_write<E, 2, DIR, double>(buf, 1, t, ns, f, v);
+    }
+    ns *= R;
+  }
+}
+
+template <int MC>
+void run_tri(int ny, int P, double s, int zero, const double* rhs, double* x) {
+  std::vector<RedRow<double>> red(2 * (size_t)P);
+  std::vector<cplx<double>> r((size_t)P * MC);
+  std::vector<double> phi((size_t)P * MC), psi((size_t)P * MC);
+  std::vector<int> j0v(P), mv(P);
+  for (int p = 0; p < P; ++p) {
+    const int j0 = (int)(((long long)p * ny) / P);
+    const int j1 = (int)(((long long)(p + 1) * ny) / P) - 1;
+    const int m = j1 - j0 + 1;
+    j0v[p] = j0;
+    mv[p] = m;
+    cplx<double>* rr = &r[(size_t)p * MC];
+    for (int i = 0; i < MC; ++i) rr[i] = mk(0.0, 0.0);
+    for (int i = 0; i < m; ++i) rr[i] = mk(rhs[2 * (j0 + i)], rhs[2 * (j0 + i) + 1]);
+    const cplx<double> rf = rr[0], rl = rr[m - 1];
+    chunk_eliminate<MC>(rr, m, s, &phi[(size_t)p * MC], &psi[(size_t)p * MC]);
+    RedRow<double> f, l;
+    chunk_reduced_rows<MC>(rr, rf, rl, m, s, p == 0, p == P - 1, &phi[(size_t)p * MC], &psi[(size_t)p * MC], f, l);
+    if (zero && p == 0) {
+      f.a = 0.0;
+      f.b = 1.0;
+      f.c = 0.0;
+      f.d = mk(0.0, 0.0);
+    }
+    red[2 * p] = f;
+    red[2 * p + 1] = l;
+  }
+  red_thomas(red.data(), 2 * P);
+  for (int p = 0; p < P; ++p) {
+    const cplx<double> xf = red[2 * p].d;
+    const cplx<double> xl = red[2 * p + 1].d;
+    const int m = mv[p], j0 = j0v[p];
+    cplx<double>* rr = &r[(size_t)p * MC];
+    const double* ph = &phi[(size_t)p * MC];
+    const double* ps = &psi[(size_t)p * MC];
+    for (int i = 1; i < m - 1; ++i) {
+      const int q = i - 1;
+      x[2 * (j0 + i)] = rr[i].re + ph[q] * xf.re + ps[q] * xl.re;
+      x[2 * (j0 + i) + 1] = rr[i].im + ph[q] * xf.im + ps[q] * xl.im;
+    }
+    x[2 * j0] = xf.re;
+    x[2 * j0 + 1] = xf.im;
+    x[2 * (j0 + m - 1)] = xl.re;
+    x[2 * (j0 + m - 1) + 1] = xl.im;
+  }
+  if (zero) {
+    double a = 0.0;
+    for (int j = 0; j < ny; ++j) a += x[2 * j];
+    for (int j = 0; j < ny; ++j) {
+      x[2 * j] -= a / ny;
+      x[2 * j + 1] = 0.0;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Radix plan of length n: returns 0 on success, fills e, tc, nst, radix[16].
+int hc_fft_plan(int n, int* e, int* tc, int* nst, int* radix) {
+  HostFft h;
+  if (!fft_factor(n, h)) return -1;
+  *e = h.e;
+  *tc = h.tc;
+  *nst = h.nst;
+  for (int s = 0; s < kMaxStages; ++s) radix[s] = h.radix[s];
+  return 0;
+}
+
+// Twiddle table exp(-2 pi i t/n), 2n doubles.
+int hc_twiddles(int n, double* out) {
+  std::vector<double> w = twiddles(n);
+  std::memcpy(out, w.data(), w.size() * sizeof(double));
+  return 0;
+}
+
+// Complex FFT of length n (interleaved re/im), dir = -1 forward, +1 inverse
+// (unnormalised), through the kernels' stage code.
+int hc_fft(int n, int dir, const double* in, double* out) {
+  HostFft h;
+  if (!fft_factor(n, h)) return -1;
+  std::vector<double> tw = twiddles(n);
+  std::vector<cplx<double>> buf(n);
+  for (int i = 0; i < n; ++i) buf[i] = mk(in[2 * i], in[2 * i + 1]);
+#define HC_CASE(EV)                                          \
+  case EV:                                                   \
+    if (dir < 0) run_fft<EV, -1>(h, tw, buf.data());         \
+    else run_fft<EV, +1>(h, tw, buf.data());                 \
+    break;
+  switch (h.e) {
+    HC_CASE(1)
+    HC_CASE(2)
+    HC_CASE(3)
+    HC_CASE(4)
+    HC_CASE(6)
+    HC_CASE(8)
+    HC_CASE(12)
+    default:
+      return -2;
+  }
+#undef HC_CASE
+  for (int i = 0; i < n; ++i) {
+    out[2 * i] = buf[i].re;
+    out[2 * i + 1] = buf[i].im;
+  }
+  return 0;
+}
+
+// One y system: x_{j-1} + beta_j x_j + x_{j+1} = rhs_j (scaled form, complex
+// interleaved), P chunks; zero != 0 applies the pin and the mean removal of
+// the (0,0) system.
+int hc_tri(int ny, int P, double s, int zero, const double* rhs, double* x) {
+  if (P < 1 || ny < 2 * P) return -1;
+  const int mmax = (ny + P - 1) / P;
+  if (mmax <= 4) run_tri<4>(ny, P, s, zero, rhs, x);
+  else if (mmax <= 8) run_tri<8>(ny, P, s, zero, rhs, x);
+  else if (mmax <= 16) run_tri<16>(ny, P, s, zero, rhs, x);
+  else return -1;
+  return 0;
+}
+
+}  // extern "C"

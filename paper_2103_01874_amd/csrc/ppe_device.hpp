@@ -1,0 +1,360 @@
+// ppe_device.hpp -- device building blocks of the projection library (gfx950).
+//
+// * complex arithmetic on (re, im) pairs,
+// * a mixed-radix (2, 3, 4, 8) Stockham FFT whose data live in LDS, one
+//   transform per group of `tc` threads, each thread holding E elements in
+//   registers during a stage (E = lcm of the radices used),
+// * the per-chunk elimination of the y-tridiagonal solve (partition method:
+//   every chunk is reduced to its two end unknowns, the reduced system is
+//   solved by one sequential sweep per system).
+//
+// Stage bodies are __host__ __device__ and take the thread index explicitly,
+// so the same code can be driven thread by thread on the host for checks;
+// the kernels call them with barriers between the read and write halves.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppe {
+
+#define PPE_HD __host__ __device__ __forceinline__
+
+template <typename T>
+struct cplx {
+  T re, im;
+};
+
+template <typename T>
+PPE_HD cplx<T> mk(T r, T i) {
+  cplx<T> c;
+  c.re = r;
+  c.im = i;
+  return c;
+}
+template <typename T>
+PPE_HD cplx<T> cadd(cplx<T> a, cplx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T>
+PPE_HD cplx<T> csub(cplx<T> a, cplx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T>
+PPE_HD cplx<T> cscale(cplx<T> a, T s) { return mk(a.re * s, a.im * s); }
+template <typename T>
+PPE_HD cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+PPE_HD cplx<T> cconj(cplx<T> a) { return mk(a.re, -a.im); }
+// multiply by -i (DIR = -1) or +i (DIR = +1)
+template <int DIR, typename T>
+PPE_HD cplx<T> mul_i(cplx<T> a) {
+  return DIR < 0 ? mk(a.im, -a.re) : mk(-a.im, a.re);
+}
+
+// ---------------------------------------------------------------------------
+// FFT plan as seen by a kernel (passed by value)
+// ---------------------------------------------------------------------------
+constexpr int kMaxStages = 16;
+
+struct FftDev {
+  int n;                   // transform length
+  int e;                   // elements per thread (lcm of the radices)
+  int tc;                  // threads per transform = n / e
+  int nst;                 // number of stages
+  int radix[kMaxStages];   // radix of each stage
+  const double* tw;        // 2*n doubles: W_n^t = exp(-2 pi i t / n), t = 0..n-1
+};
+
+// Small DFTs on registers.  DIR = -1 forward (exp(-i...)), +1 inverse.
+template <int DIR, typename T>
+PPE_HD void dft2(cplx<T>* v) {
+  cplx<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <int DIR, typename T>
+PPE_HD void dft3(cplx<T>* v) {
+  const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+  cplx<T> a = v[0], b = v[1], c = v[2];
+  cplx<T> s = cadd(b, c);
+  cplx<T> d = csub(b, c);
+  cplx<T> m = mk(a.re - T(0.5) * s.re, a.im - T(0.5) * s.im);
+  // X1 = m + DIR * i * h * d ; X2 = m - DIR * i * h * d
+  cplx<T> r = cscale(mul_i<DIR>(d), h);
+  v[0] = cadd(a, s);
+  v[1] = cadd(m, r);
+  v[2] = csub(m, r);
+}
+
+template <int DIR, typename T>
+PPE_HD void dft4(cplx<T>* v) {
+  cplx<T> a = v[0], b = v[1], c = v[2], d = v[3];
+  cplx<T> s0 = cadd(a, c), d0 = csub(a, c);
+  cplx<T> s1 = cadd(b, d), d1 = mul_i<DIR>(csub(b, d));
+  v[0] = cadd(s0, s1);
+  v[2] = csub(s0, s1);
+  v[1] = cadd(d0, d1);
+  v[3] = csub(d0, d1);
+}
+
+template <int DIR, typename T>
+PPE_HD void dft8(cplx<T>* v) {
+  const T r2 = T(0.70710678118654752440084436210485);  // 1/sqrt(2)
+  cplx<T> a[4], b[4];
+  for (int k = 0; k < 4; ++k) {
+    a[k] = cadd(v[k], v[k + 4]);
+    b[k] = csub(v[k], v[k + 4]);
+  }
+  // b_k *= W8^{k} (forward) or W8^{-k} (inverse)
+  // W8 = (1 - i)/sqrt2 forward; (1 + i)/sqrt2 inverse
+  {
+    cplx<T> t = b[1];
+    cplx<T> ti = mul_i<DIR>(t);  // DIR*i*t
+    b[1] = mk((t.re + ti.re) * r2, (t.im + ti.im) * r2);
+    b[2] = mul_i<DIR>(b[2]);
+    t = b[3];
+    ti = mul_i<DIR>(t);
+    // W8^3 = (-1 - i)/sqrt2 forward => (-t + DIR*i*t)/sqrt2
+    b[3] = mk((ti.re - t.re) * r2, (ti.im - t.im) * r2);
+  }
+  dft4<DIR>(a);
+  dft4<DIR>(b);
+  v[0] = a[0];
+  v[2] = a[1];
+  v[4] = a[2];
+  v[6] = a[3];
+  v[1] = b[0];
+  v[3] = b[1];
+  v[5] = b[2];
+  v[7] = b[3];
+}
+
+template <int R, int DIR, typename T>
+PPE_HD void dft(cplx<T>* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 3) dft3<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v);
+  else if constexpr (R == 8) dft8<DIR>(v);
+}
+
+// One Stockham stage, split into its read and write halves.
+//   element n of the transform lives at buf[n * es]
+//   butterfly j in [0, n/R): inputs j + r n/R, twiddle exp(DIR 2 pi i r (j mod Ns)/(Ns R)),
+//   outputs (j / Ns) Ns R + (j mod Ns) + r Ns.
+// Thread t owns butterflies j = t + tc q, q in [0, E/R).
+template <int E, int R, typename T, typename BufT>
+PPE_HD void stage_read(const BufT* buf, int es, int t, const FftDev& f, cplx<T>* v) {
+  constexpr int NB = E / R;
+  const int nr = f.n / R;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int j = t + f.tc * q;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const BufT x = buf[(j + r * nr) * es];
+      v[q * R + r] = mk(T(x.re), T(x.im));
+    }
+  }
+}
+
+template <int E, int R, int DIR, typename T, typename BufT>
+PPE_HD void stage_write(BufT* buf, int es, int t, int ns, const FftDev& f, cplx<T>* v) {
+  constexpr int NB = E / R;
+  const int span = ns * R;
+  const int tstep = f.n / span;  // twiddle index step: W_n^{r (j mod ns) n/(ns R)}
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int j = t + f.tc * q;
+    const int jm = j % ns;
+    const int jd = j / ns;
+    if (ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const int ti = r * jm * tstep;
+        T wr = T(f.tw[2 * ti]);
+        T wi = T(f.tw[2 * ti + 1]);
+        if (DIR > 0) wi = -wi;
+        v[q * R + r] = cmul(v[q * R + r], mk(wr, wi));
+      }
+    }
+    dft<R, DIR>(&v[q * R]);
+    const int base = jd * span + jm;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      BufT o;
+      o.re = v[q * R + r].re;
+      o.im = v[q * R + r].im;
+      buf[(base + r * ns) * es] = o;
+    }
+  }
+}
+
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+// Whole transform in LDS.  Every thread of the block must call this (it
+// contains barriers); threads with active == false only join the barriers.
+template <int E, int DIR, typename T, typename BufT>
+__device__ __forceinline__ void fft_lds(BufT* buf, int es, int t, bool active, const FftDev& f) {
+  int ns = 1;
+  for (int s = 0; s < f.nst; ++s) {
+    const int R = f.radix[s];
+    cplx<T> v[E];
+    if (R == 8) {
+      if constexpr (E % 8 == 0) {
+        if (active) stage_read<E, 8, T>(buf, es, t, f, v);
+        __syncthreads();
+        if (active) stage_write<E, 8, DIR, T>(buf, es, t, ns, f, v);
+      }
+    } else if (R == 4) {
+      if constexpr (E % 4 == 0) {
+        if (active) stage_read<E, 4, T>(buf, es, t, f, v);
+        __syncthreads();
+        if (active) stage_write<E, 4, DIR, T>(buf, es, t, ns, f, v);
+      }
+    } else if (R == 3) {
+      if constexpr (E % 3 == 0) {
+        if (active) stage_read<E, 3, T>(buf, es, t, f, v);
+        __syncthreads();
+        if (active) stage_write<E, 3, DIR, T>(buf, es, t, ns, f, v);
+      }
+    } else {
+      if constexpr (E % 2 == 0) {
+        if (active) stage_read<E, 2, T>(buf, es, t, f, v);
+        __syncthreads();
+        if (active) stage_write<E, 2, DIR, T>(buf, es, t, ns, f, v);
+      }
+    }
+    __syncthreads();
+    ns *= R;
+  }
+}
+#endif
+
+// ---------------------------------------------------------------------------
+// y-tridiagonal solve, partition method.
+//
+// Scaled system for one wavenumber pair (multiplied by dy^2):
+//   x_{j-1} + beta_j x_j + x_{j+1} = r_j,  beta_j = -2 - s (interior),
+//   beta_0 = beta_{ny-1} = -1 - s (zero-flux walls), s = -(lam_x + lam_z) dy^2 >= 0.
+// A chunk [j0, j1] (m = j1 - j0 + 1 rows) eliminates its interior rows as a
+// Dirichlet problem with end values x_{j0}, x_{j1}:
+//   x_i = y_i + phi_i x_{j0} + psi_i x_{j1},  i = 1..m-2 (local index)
+// The pivots are carried as g (den_i = -(1 + g_i)), g_1 = 1 + s,
+// g_i = s + g_{i-1}/(1 + g_{i-1}), which has no cancellation for small s.
+// The two end rows then form a tridiagonal reduced system in the ends of all
+// chunks.
+// ---------------------------------------------------------------------------
+constexpr int kMaxChunk = 16;   // longest chunk the kernels instantiate
+
+// Interior elimination, in place.  On entry r[0..m-1] holds the chunk's
+// scaled right-hand side; on exit r[1..m-2] holds y, phi[0..m-3] and
+// psi[0..m-3] the two homogeneous solutions (r[0], r[m-1] are untouched).
+template <int MC, typename T>
+PPE_HD void chunk_eliminate(cplx<T>* r, int m, T s, T* phi, T* psi) {
+  const int ni = m - 2;
+  if (ni <= 0) return;
+  T q[MC];  // 1/(1+g_i)
+  T g = T(1) + s;
+  // forward sweep: dp_i = (dp_{i-1} - r_i) q_i (den_i = -(1+g_i)); fphi_i = fphi_{i-1} q_i
+#pragma unroll
+  for (int i = 0; i < MC - 2; ++i) {
+    if (i < ni) {
+      if (i > 0) g = s + g * q[i - 1];
+      const T qi = T(1) / (T(1) + g);
+      q[i] = qi;
+      const cplx<T> ri = r[i + 1];
+      if (i == 0) {
+        r[1] = mk(-ri.re * qi, -ri.im * qi);
+        phi[0] = qi;
+      } else {
+        r[i + 1] = mk((r[i].re - ri.re) * qi, (r[i].im - ri.im) * qi);
+        phi[i] = phi[i - 1] * qi;
+      }
+    }
+  }
+  // backward sweep: x_i = dp_i + x_{i+1} q_i ; psi_last = q_last, psi_i = psi_{i+1} q_i
+#pragma unroll
+  for (int i = MC - 3; i >= 0; --i) {
+    if (i < ni) {
+      if (i == ni - 1) {
+        psi[i] = q[i];
+      } else {
+        r[i + 1] = mk(r[i + 1].re + r[i + 2].re * q[i], r[i + 1].im + r[i + 2].im * q[i]);
+        phi[i] = phi[i] + phi[i + 1] * q[i];
+        psi[i] = psi[i + 1] * q[i];
+      }
+    }
+  }
+}
+
+// The two reduced rows of a chunk (m >= 2 rows), after chunk_eliminate.
+// Unknown order: (first_0, last_0, first_1, last_1, ...).
+// first row: a * last_{p-1} + b * first_p + c * last_p = d
+// last row : a * first_p + b * last_p + c * first_{p+1} = d
+template <typename T>
+struct RedRow {
+  T a, b, c;
+  cplx<T> d;
+};
+
+template <int MC, typename T>
+PPE_HD void chunk_reduced_rows(const cplx<T>* r, const cplx<T>& r_first, const cplx<T>& r_last, int m, T s,
+                               bool global_first, bool global_last, const T* phi, const T* psi, RedRow<T>& f,
+                               RedRow<T>& l) {
+  const T beta_first = global_first ? (-T(1) - s) : (-T(2) - s);
+  const T beta_last = global_last ? (-T(1) - s) : (-T(2) - s);
+  const int ni = m - 2;
+  // x_{j0+1} = y_1 + phi_1 first + psi_1 last   (x_{j1} itself when m == 2)
+  T phi1 = T(0), psi1 = T(1), phiL = T(1), psiL = T(0);
+  cplx<T> y1 = mk(T(0), T(0)), yL = mk(T(0), T(0));
+  if (ni > 0) {
+    phi1 = phi[0];
+    psi1 = psi[0];
+    y1 = r[1];
+#pragma unroll
+    for (int i = 0; i < MC - 2; ++i)
+      if (i == ni - 1) {
+        phiL = phi[i];
+        psiL = psi[i];
+        yL = r[i + 1];
+      }
+  }
+  f.a = global_first ? T(0) : T(1);
+  f.b = beta_first + phi1;
+  f.c = psi1;
+  f.d = csub(r_first, y1);
+  l.a = phiL;
+  l.b = beta_last + psiL;
+  l.c = global_last ? T(0) : T(1);
+  l.d = csub(r_last, yL);
+}
+
+// Sequential Thomas sweep over the n reduced rows of one system, in place:
+// on exit rows[i].d holds the unknown i (rows[i].b is set to 1).  The
+// reduced system inherits weak diagonal dominance from the y operator; a
+// plain sweep keeps its backward error at rounding level for the low modes,
+// where cyclic reduction loses about two digits.
+template <typename T>
+PPE_HD void red_thomas(RedRow<T>* rows, int n) {
+  // forward: c'_i = c_i / den, d'_i = (d_i - a_i d'_{i-1}) / den, den = b_i - a_i c'_{i-1}
+  T cp = T(0);
+  cplx<T> dp = mk(T(0), T(0));
+  for (int i = 0; i < n; ++i) {
+    const RedRow<T> r = rows[i];
+    const T inv = T(1) / (r.b - r.a * cp);
+    cp = r.c * inv;
+    dp = mk((r.d.re - r.a * dp.re) * inv, (r.d.im - r.a * dp.im) * inv);
+    rows[i].c = cp;
+    rows[i].d = dp;
+  }
+  // backward: x_i = d'_i - c'_i x_{i+1}
+  cplx<T> x = rows[n - 1].d;
+  rows[n - 1].b = T(1);
+  for (int i = n - 2; i >= 0; --i) {
+    const RedRow<T> r = rows[i];
+    x = mk(r.d.re - r.c * x.re, r.d.im - r.c * x.im);
+    rows[i].d = x;
+    rows[i].b = T(1);
+  }
+}
+
+}  // namespace ppe

@@ -1,0 +1,100 @@
+// ppe_kernels.hpp -- HIP kernels of the split pressure-gradient projection
+// (Poblador-Ibanez & Sirignano, arXiv 2103.01874, Sec. 5.4).
+//
+// Pass structure of one solve (every pass is one launch over all instances
+// of a batch; blockIdx.z is the instance):
+//   k_assemble   b = (rho0/dt)(D u* - S) + D(beta_f G p_hat)  (Eq. 29) fused
+//                with the real FFT along x (two rows packed per complex FFT)
+//   k_fft_z      complex FFT along z, in place on the half spectrum
+//   k_tri        one tridiagonal system in y per (kx, kz), partition method;
+//                the (0,0) system (singular) is compatible-projected, pinned
+//                and gauge-fixed in FP64 from FP64 plane sums
+//   k_fft_z      inverse
+//   k_c2r        inverse real FFT along x -> p (or p update when refining)
+//   k_residual   FP64 r = b - L p fused with the real FFT of r (refinement)
+//   k_correct    u^{n+1} = u* - dt[G p/rho0 + gamma_f G p_hat]  (Eq. 28) and
+//                the continuity residual of the result
+#pragma once
+
+#include "ppe_device.hpp"
+
+namespace ppe {
+
+constexpr int kMaxLaunch = 16;     // instances per launch (kernel-argument table)
+constexpr int kNScal = 16;         // per-instance scalar slots
+constexpr int kRedBlocks = 2048;   // grid cap of the grid-stride reduction kernels
+
+enum ScalarSlot {
+  SC_RHO0 = 0,    // rho0 used
+  SC_DT,          // dt
+  SC_COMPAT,      // mean(D u* - S)
+  SC_REF2,        // ||(rho0/dt)(D u* - S_c)||^2  (refinement stop scale)
+  SC_BMEAN,       // mean(b)
+  SC_PMEAN,       // mean of the current p (refinement)
+  SC_CONV,        // 1 once the refinement met tol
+  SC_RES,         // last relative residual
+  SC_ITERS,       // refinement sweeps run
+  SC_RHO0_BITS,   // min(rho) accumulator (uint64 bits of a positive double)
+  SC_TOL,         // tol
+};
+
+struct InstPtrs {
+  const double* us;
+  const double* vs;
+  const double* ws;
+  const double* rho;
+  const double* pn;
+  const double* pnm1;
+  const double* S;
+  double* p;
+  double* u;
+  double* v;
+  double* w;
+  void* info;     // ppe_info_t*
+  double rho0_in;
+  double dt;
+};
+
+struct PtrTable {
+  InstPtrs in[kMaxLaunch];
+};
+
+struct Geom {
+  int nx, ny, nz, hx;
+  long long npts;       // nx*ny*nz
+  long long spec_elems; // nz*ny*hx
+  double idx, idy, idz; // 1/dx, 1/dy, 1/dz
+  double dy2;           // dy^2
+  double inv_nxnz;      // 1/(nx*nz)
+};
+
+// Workspace seen by the kernels (device pointers, per-instance strides).
+template <typename TS>
+struct Work {
+  cplx<TS>* spec;       // [inst][nz][ny][hx]
+  double* b64;          // [inst][npts]        (refinement only)
+  double* rowsum;       // [inst][nz][ny]      FP64 row sums of the transformed field
+  double* colsum;       // [inst][ny]          FP64 plane sums (zero mode)
+  double* scal;         // [inst][kNScal]
+  double* partial;      // [inst][pstride] per-block partial sums
+  long long pstride;    // doubles of partials per instance
+  unsigned* counter;    // [inst][8]
+  const double* lamx;   // [hx]  lam_x(kx)
+  const double* lamz;   // [nz]  lam_z(kz)
+  int inst0;            // first instance of this launch in the workspace
+};
+
+// ppe_info_t as laid out in include/ppe.h
+struct InfoRec {
+  int32_t status;
+  int32_t iters;
+  double rho0_used;
+  double compat_defect;
+  double res_rel;
+  double div_l2;
+  double div_max;
+  double div0_l2;
+  double p_mean;
+};
+
+}  // namespace ppe

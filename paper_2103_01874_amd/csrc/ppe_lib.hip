@@ -1,0 +1,478 @@
+// ppe_lib.hip -- plan, launch orchestration and the C ABI of include/ppe.h.
+//
+// One projection step of Poblador-Ibanez & Sirignano (arXiv 2103.01874),
+// Sec. 5.4: right-hand side of Eq. (29), direct FFT/tridiagonal Poisson
+// solve, projection of Eq. (28).  All arithmetic runs in the kernels of
+// ppe_kernels.hip.inc; this file validates arguments, owns device memory and
+// enqueues launches on the plan's stream.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ppe.h"
+#include "ppe_kernels.hpp"
+#include "ppe_kernels.hip.inc"
+#include "ppe_plan_util.hpp"
+
+using namespace ppe;
+
+static_assert(sizeof(ppe_info_t) == sizeof(InfoRec), "ppe_info_t layout");
+static_assert(sizeof(PtrTable) <= 4096, "kernel argument table too large");
+
+namespace {
+
+FftDev to_dev(const HostFft& h) {
+  FftDev d;
+  d.n = h.n;
+  d.e = h.e;
+  d.tc = h.tc;
+  d.nst = h.nst;
+  for (int s = 0; s < kMaxStages; ++s) d.radix[s] = h.radix[s];
+  d.tw = h.tw;
+  return d;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct ppe_plan_s {
+  ppe_desc_t d;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Geom g;
+  HostFft fx, fz;
+  // launch shapes
+  int rp = 1;            // row pairs per block (x kernels)
+  int tx = 1;            // kx columns per block (z FFT)
+  int txs = 1, pch = 1;  // systems per block, chunks per system (tri)
+  int mc = 16;           // register rows per chunk (template of k_tri)
+  size_t lds_x = 0, lds_z = 0, lds_t = 0;
+  long long pstride = 0;
+  // device memory
+  void* spec = nullptr;
+  double* b64 = nullptr;
+  double* rowsum = nullptr;
+  double* colsum = nullptr;
+  double* scal = nullptr;
+  double* partial = nullptr;
+  unsigned* counter = nullptr;
+  double* lamx = nullptr;
+  double* lamz = nullptr;
+  size_t bytes = 0;
+};
+
+namespace {
+
+bool desc_ok(const ppe_desc_t* d) {
+  if (!d) return false;
+  if (d->nx < 1 || d->nz < 1 || d->ny < 2) return false;
+  if (d->nx > kMaxN || d->nz > kMaxN || d->ny > kMaxN) return false;
+  if (!(d->lx > 0) || !(d->ly > 0) || !(d->lz > 0)) return false;
+  if (d->precision != PPE_PREC_FP64 && d->precision != PPE_PREC_MIXED) return false;
+  if (d->batch < 1 || d->batch > PPE_MAX_BATCH) return false;
+  if (d->max_refine < 0 || d->max_refine > 64) return false;
+  if (!(d->tol >= 0)) return false;
+  return true;
+}
+
+size_t spec_elem_bytes(const ppe_desc_t* d) {
+  return d->precision == PPE_PREC_FP64 ? 2 * sizeof(double) : 2 * sizeof(float);
+}
+
+// Launch shapes and workspace sizes; fills p (no allocation).
+bool shape_plan(ppe_plan_s* p) {
+  const ppe_desc_t& d = p->d;
+  if (!fft_factor(d.nx, p->fx) || !fft_factor(d.nz, p->fz)) return false;
+  Geom& g = p->g;
+  g.nx = d.nx;
+  g.ny = d.ny;
+  g.nz = d.nz;
+  g.hx = d.nx / 2 + 1;
+  g.npts = (long long)d.nx * d.ny * d.nz;
+  g.spec_elems = (long long)d.nz * d.ny * g.hx;
+  const double dx = d.lx / d.nx, dy = d.ly / d.ny, dz = d.lz / d.nz;
+  g.idx = 1.0 / dx;
+  g.idy = 1.0 / dy;
+  g.idz = 1.0 / dz;
+  g.dy2 = dy * dy;
+  g.inv_nxnz = 1.0 / ((double)d.nx * (double)d.nz);
+  // x kernels: RP row pairs of tc threads
+  const int tcx = p->fx.tc;
+  if (tcx > 512) return false;
+  p->rp = std::max(1, 256 / tcx);
+  while (p->rp > 1 && ((size_t)p->rp * d.nx * 16 + (size_t)p->rp * tcx * 8 > 65536 || p->rp * tcx > 512)) p->rp /= 2;
+  p->lds_x = (size_t)p->rp * d.nx * 16 + (size_t)p->rp * tcx * 8;
+  // z FFT: TX columns of tc threads
+  const int tcz = p->fz.tc;
+  if (tcz > 512) return false;
+  p->tx = std::max(1, std::min(16, 512 / tcz));
+  while (p->tx > 1 && ((size_t)d.nz * p->tx * 16 > 65536 || p->tx * tcz > 512)) p->tx /= 2;
+  p->lds_z = std::max((size_t)d.nz * p->tx * 16, (size_t)p->tx * tcz * 8);
+  // tri: P chunks of 2..16 rows, TXS systems per block
+  int P = (int)std::lround(d.ny / 8.0);
+  P = std::max(P, (d.ny + kMaxChunk - 1) / kMaxChunk);
+  P = std::min(P, d.ny / 2);
+  P = std::max(P, 1);
+  p->pch = P;
+  p->txs = std::max(1, 256 / P);
+  if (p->txs * P > 256) return false;
+  const int mmax = (d.ny + P - 1) / P;
+  p->mc = mmax <= 4 ? 4 : (mmax <= 8 ? 8 : 16);
+  p->lds_t = std::max((size_t)p->txs * 2 * P * sizeof(RedRow<double>), (size_t)p->txs * P * 8);
+  if (p->lds_x > 65536 || p->lds_z > 65536 || p->lds_t > 65536) return false;
+  // per-instance partial-sum stride: the largest grid.x of a reducing kernel
+  const long long nrows = (long long)d.ny * d.nz;
+  const long long npairs = (nrows + 1) / 2;
+  const long long gx = (npairs + p->rp - 1) / p->rp;
+  long long gmax = std::max<long long>(gx, kRedBlocks);
+  p->pstride = 4 * gmax;
+  return true;
+}
+
+size_t workspace_bytes(const ppe_plan_s* p) {
+  const ppe_desc_t& d = p->d;
+  const size_t B = (size_t)d.batch;
+  size_t s = 0;
+  s += B * (size_t)p->g.spec_elems * spec_elem_bytes(&d);
+  if (d.precision == PPE_PREC_MIXED) s += B * (size_t)p->g.npts * 8;
+  s += B * (size_t)d.ny * d.nz * 8;   // rowsum
+  s += B * (size_t)d.ny * 8;          // colsum
+  s += B * (size_t)kNScal * 8;        // scalars
+  s += B * (size_t)p->pstride * 8;    // partials
+  s += B * 8 * sizeof(unsigned);      // counters
+  s += (size_t)(d.nx / 2 + 1) * 8 + (size_t)d.nz * 8;  // eigenvalue tables
+  s += (size_t)2 * d.nx * 8 + (size_t)2 * d.nz * 8;    // twiddles
+  return s;
+}
+
+template <typename T>
+hipError_t dalloc(ppe_plan_s* p, T** ptr, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc((void**)ptr, bytes);
+  if (e == hipSuccess) p->bytes += bytes;
+  return e;
+}
+
+void free_plan(ppe_plan_s* p) {
+  if (!p) return;
+  void* ptrs[] = {p->spec, p->b64, p->rowsum, p->colsum, p->scal, p->partial, p->counter,
+                  p->lamx, p->lamz, p->fx.tw, p->fz.tw};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+template <typename TS>
+Work<TS> make_work(ppe_plan_s* p, int inst0) {
+  Work<TS> w;
+  w.spec = reinterpret_cast<cplx<TS>*>(p->spec);
+  w.b64 = p->b64;
+  w.rowsum = p->rowsum;
+  w.colsum = p->colsum;
+  w.scal = p->scal;
+  w.partial = p->partial;
+  w.pstride = p->pstride;
+  w.counter = p->counter;
+  w.lamx = p->lamx;
+  w.lamz = p->lamz;
+  w.inst0 = inst0;
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// E dispatch for the FFT kernels
+// ---------------------------------------------------------------------------
+#define PPE_E_SWITCH(EVAL, CALL)  \
+  switch (EVAL) {                 \
+    case 1: { constexpr int E = 1; CALL; } break;   \
+    case 2: { constexpr int E = 2; CALL; } break;   \
+    case 3: { constexpr int E = 3; CALL; } break;   \
+    case 4: { constexpr int E = 4; CALL; } break;   \
+    case 6: { constexpr int E = 6; CALL; } break;   \
+    case 8: { constexpr int E = 8; CALL; } break;   \
+    case 12: { constexpr int E = 12; CALL; } break; \
+    default: return PPE_ERR_UNSUPPORTED;            \
+  }
+
+template <typename TS>
+ppe_status_t launch_fft_z(ppe_plan_s* p, const Work<TS>& W, int nb, int dir, int check) {
+  const Geom& g = p->g;
+  dim3 grid(g.ny, (g.hx + p->tx - 1) / p->tx, nb);
+  dim3 block(p->tx * p->fz.tc);
+  FftDev fz = to_dev(p->fz);
+  if (dir < 0) {
+    PPE_E_SWITCH(fz.e, (k_fft_z<TS, E, -1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check)));
+  } else {
+    PPE_E_SWITCH(fz.e, (k_fft_z<TS, E, +1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check)));
+  }
+  return PPE_OK;
+}
+
+template <typename TS>
+ppe_status_t launch_chain(ppe_plan_s* p, const Work<TS>& W, int nb, int check) {
+  const Geom& g = p->g;
+  ppe_status_t st = launch_fft_z<TS>(p, W, nb, -1, check);
+  if (st != PPE_OK) return st;
+  dim3 tgrid((g.hx + p->txs - 1) / p->txs, g.nz, nb);
+  dim3 tblock(p->txs * p->pch);
+  if (p->mc == 4)
+    k_tri<TS, 4><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+  else if (p->mc == 8)
+    k_tri<TS, 8><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+  else
+    k_tri<TS, 16><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+  return launch_fft_z<TS>(p, W, nb, +1, check);
+}
+
+template <typename TS>
+ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) {
+  const Geom& g = p->g;
+  Work<TS> W = make_work<TS>(p, inst0);
+  const bool mixed = p->d.precision == PPE_PREC_MIXED;
+  const double tol = mixed ? p->d.tol : 0.0;
+  k_prologue<<<1, 64, 0, p->stream>>>(tab, p->scal, p->counter, inst0, nb, tol);
+  bool need_min = false;
+  for (int i = 0; i < nb; ++i) need_min |= !(tab.in[i].rho0_in > 0.0);
+  if (need_min) {
+    const long long blocks = std::min<long long>((g.npts + 255) / 256, 1024);
+    k_rho_min<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->scal, inst0);
+    k_rho_min_finish<<<1, 64, 0, p->stream>>>(tab, p->scal, inst0, nb);
+  }
+  const long long nrows = (long long)g.ny * g.nz;
+  const long long npairs = (nrows + 1) / 2;
+  dim3 xgrid((unsigned)((npairs + p->rp - 1) / p->rp), 1, nb);
+  dim3 xblock(p->rp * p->fx.tc);
+  FftDev fx = to_dev(p->fx);
+  PPE_E_SWITCH(fx.e, (k_assemble<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, mixed ? 1 : 0)));
+  ppe_status_t st = launch_chain<TS>(p, W, nb, 0);
+  if (st != PPE_OK) return st;
+  PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 0, 0)));
+  if (mixed) {
+    for (int it = 0; it < p->d.max_refine; ++it) {
+      PPE_E_SWITCH(fx.e, (k_residual<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp)));
+      st = launch_chain<TS>(p, W, nb, 1);
+      if (st != PPE_OK) return st;
+      PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1)));
+    }
+  }
+  return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
+}
+
+bool ptrs_ok(const void* const* a, int n) {
+  if (!a) return false;
+  for (int i = 0; i < n; ++i)
+    if (!a[i]) return false;
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t ppe_plan_workspace_bytes(const ppe_desc_t* desc) {
+  if (!desc_ok(desc)) return 0;
+  ppe_plan_s tmp;
+  tmp.d = *desc;
+  if (!shape_plan(&tmp)) return 0;
+  return workspace_bytes(&tmp);
+}
+
+ppe_status_t ppe_plan(const ppe_desc_t* desc, void* stream, ppe_plan_t* out) {
+  if (!out) return PPE_ERR_ARG;
+  *out = nullptr;
+  if (!desc_ok(desc)) return PPE_ERR_ARG;
+  ppe_plan_s* p = new (std::nothrow) ppe_plan_s();
+  if (!p) return PPE_ERR_NOMEM;
+  p->d = *desc;
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  if (!shape_plan(p)) {
+    delete p;
+    return PPE_ERR_UNSUPPORTED;
+  }
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return PPE_ERR_DEVICE;
+  }
+  const ppe_desc_t& d = p->d;
+  const size_t B = (size_t)d.batch;
+  bool ok = true;
+  ok &= dalloc(p, (char**)&p->spec, B * (size_t)p->g.spec_elems * spec_elem_bytes(&d)) == hipSuccess;
+  if (d.precision == PPE_PREC_MIXED) ok &= dalloc(p, &p->b64, B * (size_t)p->g.npts * 8) == hipSuccess;
+  ok &= dalloc(p, &p->rowsum, B * (size_t)d.ny * d.nz * 8) == hipSuccess;
+  ok &= dalloc(p, &p->colsum, B * (size_t)d.ny * 8) == hipSuccess;
+  ok &= dalloc(p, &p->scal, B * kNScal * 8) == hipSuccess;
+  ok &= dalloc(p, &p->partial, B * (size_t)p->pstride * 8) == hipSuccess;
+  ok &= dalloc(p, &p->counter, B * 8 * sizeof(unsigned)) == hipSuccess;
+  ok &= dalloc(p, &p->lamx, (size_t)p->g.hx * 8) == hipSuccess;
+  ok &= dalloc(p, &p->lamz, (size_t)d.nz * 8) == hipSuccess;
+  ok &= dalloc(p, &p->fx.tw, (size_t)2 * d.nx * 8) == hipSuccess;
+  ok &= dalloc(p, &p->fz.tw, (size_t)2 * d.nz * 8) == hipSuccess;
+  if (!ok) {
+    free_plan(p);
+    return PPE_ERR_NOMEM;
+  }
+  // modified wavenumbers of the periodic directions (closed form of the
+  // 3-point second difference on its Fourier modes)
+  const double dx = d.lx / d.nx, dz = d.lz / d.nz;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  std::vector<double> lx(p->g.hx), lz(d.nz);
+  for (int a = 0; a < p->g.hx; ++a) {
+    const long double s = sinl(pi * a / d.nx);
+    lx[a] = (double)(-4.0L / ((long double)dx * dx) * s * s);
+  }
+  for (int c = 0; c < d.nz; ++c) {
+    const long double s = sinl(pi * c / d.nz);
+    lz[c] = (double)(-4.0L / ((long double)dz * dz) * s * s);
+  }
+  std::vector<double> twx = twiddles(d.nx), twz = twiddles(d.nz);
+  ok &= hipMemcpy(p->lamx, lx.data(), lx.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+  ok &= hipMemcpy(p->lamz, lz.data(), lz.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+  ok &= hipMemcpy(p->fx.tw, twx.data(), twx.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+  ok &= hipMemcpy(p->fz.tw, twz.data(), twz.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+  ok &= hipMemset(p->counter, 0, B * 8 * sizeof(unsigned)) == hipSuccess;
+  if (!ok) {
+    free_plan(p);
+    return PPE_ERR_DEVICE;
+  }
+  *out = p;
+  return PPE_OK;
+}
+
+ppe_status_t ppe_plan_destroy(ppe_plan_t plan) {
+  if (!plan) return PPE_ERR_ARG;
+  (void)hipStreamSynchronize(plan->stream);
+  free_plan(plan);
+  return PPE_OK;
+}
+
+ppe_status_t ppe_plan_set_stream(ppe_plan_t plan, void* stream) {
+  if (!plan) return PPE_ERR_ARG;
+  plan->stream = reinterpret_cast<hipStream_t>(stream);
+  return PPE_OK;
+}
+
+ppe_status_t ppe_solve(ppe_plan_t p, const double* rho0, const double* dt, const double* const* us,
+                       const double* const* vs, const double* const* ws, const double* const* rho,
+                       const double* const* pn, const double* const* pnm1, const double* const* S,
+                       double* const* pout, ppe_info_t* info) {
+  if (!p || !rho0 || !dt || !info) return PPE_ERR_ARG;
+  const int B = p->d.batch;
+  if (!ptrs_ok((const void* const*)us, B) || !ptrs_ok((const void* const*)vs, B) ||
+      !ptrs_ok((const void* const*)ws, B) || !ptrs_ok((const void* const*)rho, B) ||
+      !ptrs_ok((const void* const*)pn, B) || !ptrs_ok((const void* const*)pnm1, B) ||
+      !ptrs_ok((const void* const*)S, B) || !ptrs_ok((const void* const*)pout, B))
+    return PPE_ERR_ARG;
+  for (int i = 0; i < B; ++i)
+    if (!(dt[i] > 0) || !std::isfinite(dt[i]) || std::isnan(rho0[i])) return PPE_ERR_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
+  for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
+    const int nb = std::min(kMaxLaunch, B - i0);
+    PtrTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    for (int i = 0; i < nb; ++i) {
+      InstPtrs& q = tab.in[i];
+      q.us = us[i0 + i];
+      q.vs = vs[i0 + i];
+      q.ws = ws[i0 + i];
+      q.rho = rho[i0 + i];
+      q.pn = pn[i0 + i];
+      q.pnm1 = pnm1[i0 + i];
+      q.S = S[i0 + i];
+      q.p = pout[i0 + i];
+      q.info = info + i0 + i;
+      q.rho0_in = rho0[i0 + i];
+      q.dt = dt[i0 + i];
+    }
+    ppe_status_t st = (p->d.precision == PPE_PREC_FP64) ? solve_typed<double>(p, tab, i0, nb)
+                                                         : solve_typed<float>(p, tab, i0, nb);
+    if (st != PPE_OK) return st;
+  }
+  return PPE_OK;
+}
+
+ppe_status_t ppe_correct(ppe_plan_t p, const double* dt, const double* const* us, const double* const* vs,
+                         const double* const* ws, const double* const* rho, const double* const* pn,
+                         const double* const* pnm1, const double* const* pin, const double* const* S,
+                         double* const* u, double* const* v, double* const* w, ppe_info_t* info) {
+  if (!p || !dt || !info) return PPE_ERR_ARG;
+  const int B = p->d.batch;
+  if (!ptrs_ok((const void* const*)us, B) || !ptrs_ok((const void* const*)vs, B) ||
+      !ptrs_ok((const void* const*)ws, B) || !ptrs_ok((const void* const*)rho, B) ||
+      !ptrs_ok((const void* const*)pn, B) || !ptrs_ok((const void* const*)pnm1, B) ||
+      !ptrs_ok((const void* const*)pin, B) || !ptrs_ok((const void* const*)S, B) ||
+      !ptrs_ok((const void* const*)u, B) || !ptrs_ok((const void* const*)v, B) || !ptrs_ok((const void* const*)w, B))
+    return PPE_ERR_ARG;
+  for (int i = 0; i < B; ++i)
+    if (!(dt[i] > 0) || !std::isfinite(dt[i])) return PPE_ERR_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
+  const Geom& g = p->g;
+  const double tol = p->d.precision == PPE_PREC_MIXED ? p->d.tol : 0.0;
+  for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
+    const int nb = std::min(kMaxLaunch, B - i0);
+    PtrTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    for (int i = 0; i < nb; ++i) {
+      InstPtrs& q = tab.in[i];
+      q.us = us[i0 + i];
+      q.vs = vs[i0 + i];
+      q.ws = ws[i0 + i];
+      q.rho = rho[i0 + i];
+      q.pn = pn[i0 + i];
+      q.pnm1 = pnm1[i0 + i];
+      q.S = S[i0 + i];
+      q.p = const_cast<double*>(pin[i0 + i]);
+      q.u = u[i0 + i];
+      q.v = v[i0 + i];
+      q.w = w[i0 + i];
+      q.info = info + i0 + i;
+      q.dt = dt[i0 + i];
+    }
+    const long long blocks = std::min<long long>((g.npts + 255) / 256, kRedBlocks);
+    k_correct<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->partial, p->pstride, p->counter, i0,
+                                                                     tol);
+  }
+  return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
+}
+
+ppe_status_t ppe_residual(ppe_plan_t p, const double* const* u, const double* const* v, const double* const* w,
+                          const double* const* S, double* out) {
+  if (!p || !out) return PPE_ERR_ARG;
+  const int B = p->d.batch;
+  if (!ptrs_ok((const void* const*)u, B) || !ptrs_ok((const void* const*)v, B) ||
+      !ptrs_ok((const void* const*)w, B) || !ptrs_ok((const void* const*)S, B))
+    return PPE_ERR_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
+  const Geom& g = p->g;
+  for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
+    const int nb = std::min(kMaxLaunch, B - i0);
+    PtrTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    for (int i = 0; i < nb; ++i) {
+      InstPtrs& q = tab.in[i];
+      q.u = const_cast<double*>(u[i0 + i]);
+      q.v = const_cast<double*>(v[i0 + i]);
+      q.w = const_cast<double*>(w[i0 + i]);
+      q.S = S[i0 + i];
+    }
+    const long long blocks = std::min<long long>((g.npts + 255) / 256, kRedBlocks);
+    for (int pass = 0; pass < 2; ++pass)
+      k_div_stats<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->partial, p->pstride, p->counter,
+                                                                         out + 3 * (size_t)i0, i0, pass);
+  }
+  return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
+}
+
+const char* ppe_version(void) { return "ppe-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

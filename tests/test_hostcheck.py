@@ -1,0 +1,106 @@
+"""CPU checks of the kernels' stage code (FFT stages, y-tridiagonal chunks).
+
+libppe_hostcheck.so drives the same __host__ __device__ stage functions the
+HIP kernels execute, thread by thread with the kernels' barrier placement.
+Expected values come from numpy's FFT and a dense numpy solve.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(os.path.dirname(HERE), "paper_2103_01874_amd", "libppe_hostcheck.so")
+
+
+@pytest.fixture(scope="module")
+def hc():
+    if not os.path.exists(LIB):
+        pytest.skip("libppe_hostcheck.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.hc_fft.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+    lib.hc_tri.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp]
+    lib.hc_fft_plan.argtypes = [ctypes.c_int, ip, ip, ip, ip]
+    lib.hc_twiddles.argtypes = [ctypes.c_int, dp]
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+SIZES = [1, 2, 3, 4, 6, 8, 9, 12, 16, 18, 24, 27, 32, 36, 48, 64, 96, 128, 192, 256, 384, 512, 1024, 2048]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_fft_stages_match_numpy(hc, n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    xin = np.ascontiguousarray(np.stack([x.real, x.imag], -1).ravel())
+    out = np.zeros(2 * n)
+    assert hc.hc_fft(n, -1, _p(xin), _p(out)) == 0
+    y = out[0::2] + 1j * out[1::2]
+    assert np.abs(y - np.fft.fft(x)).max() < 1e-14 * np.sqrt(n) * np.abs(x).sum() / np.sqrt(n) + 1e-15
+    assert hc.hc_fft(n, +1, _p(xin), _p(out)) == 0
+    y = out[0::2] + 1j * out[1::2]
+    assert np.abs(y - n * np.fft.ifft(x)).max() < 1e-14 * np.abs(x).sum() + 1e-15
+
+
+def test_fft_rejects_other_primes(hc):
+    e, tc, nst = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    rad = (ctypes.c_int * 16)()
+    for n in (5, 7, 10, 14, 25, 4096):
+        assert hc.hc_fft_plan(n, ctypes.byref(e), ctypes.byref(tc), ctypes.byref(nst), rad) != 0
+    assert hc.hc_fft_plan(192, ctypes.byref(e), ctypes.byref(tc), ctypes.byref(nst), rad) == 0
+    assert (e.value, tc.value, list(rad)[: nst.value]) == (12, 16, [3, 4, 4, 4])
+
+
+def test_twiddles_accurate(hc):
+    for n in (6, 96, 512):
+        w = np.zeros(2 * n)
+        hc.hc_twiddles(n, _p(w))
+        # reference in extended precision (x87 long double), rounded once
+        pi_ld = np.arctan(np.longdouble(1)) * 4
+        a = 2 * pi_ld * np.arange(n, dtype=np.longdouble) / n
+        assert np.abs(w[0::2] - np.cos(a).astype(np.float64)).max() <= 1.2e-16
+        assert np.abs(w[1::2] + np.sin(a).astype(np.float64)).max() <= 1.2e-16
+
+
+def _dense(ny, s):
+    A = np.diag(np.full(ny, -2.0 - s)) + np.diag(np.ones(ny - 1), 1) + np.diag(np.ones(ny - 1), -1)
+    A[0, 0] = A[-1, -1] = -1.0 - s
+    return A
+
+
+@pytest.mark.parametrize("ny,P", [(2, 1), (3, 1), (5, 2), (8, 1), (8, 4), (32, 4), (64, 8), (96, 12),
+                                  (128, 16), (256, 32), (255, 32), (100, 7), (16, 1)])
+@pytest.mark.parametrize("s", [1e-6, 0.37, 25.0])
+def test_tri_chunks_match_dense(hc, ny, P, s):
+    rng = np.random.default_rng(ny * 31 + P)
+    rhs = rng.standard_normal(ny) + 1j * rng.standard_normal(ny)
+    rin = np.ascontiguousarray(np.stack([rhs.real, rhs.imag], -1).ravel())
+    out = np.zeros(2 * ny)
+    assert hc.hc_tri(ny, P, s, 0, _p(rin), _p(out)) == 0
+    x = out[0::2] + 1j * out[1::2]
+    want = np.linalg.solve(_dense(ny, s), rhs)
+    cond = np.linalg.cond(_dense(ny, s))
+    assert np.abs(x - want).max() <= 1e-15 * cond * np.abs(want).max() * 10
+
+
+@pytest.mark.parametrize("ny,P", [(4, 2), (32, 4), (96, 12), (256, 32)])
+def test_tri_zero_mode_pin_and_gauge(hc, ny, P):
+    rng = np.random.default_rng(ny)
+    rhs = rng.standard_normal(ny)
+    rhs -= rhs.mean()
+    rin = np.ascontiguousarray(np.stack([rhs, 0 * rhs], -1).ravel())
+    out = np.zeros(2 * ny)
+    assert hc.hc_tri(ny, P, 0.0, 1, _p(rin), _p(out)) == 0
+    x = out[0::2]
+    A = _dense(ny, 0.0)
+    assert abs(x.mean()) < 1e-12 * np.abs(x).max()
+    assert np.abs(A @ x - rhs).max() < 1e-14 * np.abs(A).max() * np.abs(x).max()
+    ls = np.linalg.lstsq(A, rhs, rcond=None)[0]
+    assert np.abs(x - (ls - ls.mean())).max() < 1e-9 * np.abs(x).max()
