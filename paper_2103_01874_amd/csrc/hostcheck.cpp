@@ -16,7 +16,7 @@ using namespace ppe;
 
 namespace {
 
-template <int E, int DIR>
+template <int E, int DIR, bool PAD>
 void run_fft(const HostFft& h, const std::vector<double>& tw, cplx<double>* buf) {
   FftDev f;
   f.n = h.n;
@@ -32,17 +32,17 @@ void run_fft(const HostFft& h, const std::vector<double>& tw, cplx<double>* buf)
     // read half for every thread, then write half for every thread
     for (int t = 0; t < f.tc; ++t) {
       cplx<double>* v = &regs[(size_t)t * E];
-      if constexpr (E % 8 == 0) if (R == 8) stage_read<E, 8, double>(buf, 1, t, f, v);
-      if constexpr (E % 4 == 0) if (R == 4) stage_read<E, 4, double>(buf, 1, t, f, v);
-      if constexpr (E % 3 == 0) if (R == 3) stage_read<E, 3, double>(buf, 1, t, f, v);
-      if constexpr (E % 2 == 0) if (R == 2) stage_read<E, 2, double>(buf, 1, t, f, v);
+      if constexpr (E % 8 == 0) if (R == 8) stage_read<E, 8, PAD, double>(buf, 1, t, f, v);
+      if constexpr (E % 4 == 0) if (R == 4) stage_read<E, 4, PAD, double>(buf, 1, t, f, v);
+      if constexpr (E % 3 == 0) if (R == 3) stage_read<E, 3, PAD, double>(buf, 1, t, f, v);
+      if constexpr (E % 2 == 0) if (R == 2) stage_read<E, 2, PAD, double>(buf, 1, t, f, v);
     }
     for (int t = 0; t < f.tc; ++t) {
       cplx<double>* v = &regs[(size_t)t * E];
-      if constexpr (E % 8 == 0) if (R == 8) stage_write<E, 8, DIR, double>(buf, 1, t, ns, f, v);
-      if constexpr (E % 4 == 0) if (R == 4) stage_write<E, 4, DIR, double>(buf, 1, t, ns, f, v);
-      if constexpr (E % 3 == 0) if (R == 3) stage_write<E, 3, DIR, double>(buf, 1, t, ns, f, v);
-      if constexpr (E % 2 == 0) if (R == 2) stage_write<E, 2, DIR, double>(buf, 1, t, ns, f, v);
+      if constexpr (E % 8 == 0) if (R == 8) stage_write<E, 8, DIR, PAD, double>(buf, 1, t, ns, f, v);
+      if constexpr (E % 4 == 0) if (R == 4) stage_write<E, 4, DIR, PAD, double>(buf, 1, t, ns, f, v);
+      if constexpr (E % 3 == 0) if (R == 3) stage_write<E, 3, DIR, PAD, double>(buf, 1, t, ns, f, v);
+      if constexpr (E % 2 == 0) if (R == 2) stage_write<E, 2, DIR, PAD, double>(buf, 1, t, ns, f, v);
     }
     ns *= R;
   }
@@ -132,12 +132,13 @@ int hc_fft(int n, int dir, const double* in, double* out) {
   HostFft h;
   if (!fft_factor(n, h)) return -1;
   std::vector<double> tw = twiddles(n);
-  std::vector<cplx<double>> buf(n);
-  for (int i = 0; i < n; ++i) buf[i] = mk(in[2 * i], in[2 * i + 1]);
+  // padded row layout, as the row kernels use it
+  std::vector<cplx<double>> buf(padded_len(n));
+  for (int i = 0; i < n; ++i) buf[lslot<true>(i, 1)] = mk(in[2 * i], in[2 * i + 1]);
 #define HC_CASE(EV)                                          \
   case EV:                                                   \
-    if (dir < 0) run_fft<EV, -1>(h, tw, buf.data());         \
-    else run_fft<EV, +1>(h, tw, buf.data());                 \
+    if (dir < 0) run_fft<EV, -1, true>(h, tw, buf.data());   \
+    else run_fft<EV, +1, true>(h, tw, buf.data());           \
     break;
   switch (h.e) {
     HC_CASE(1)
@@ -152,8 +153,8 @@ int hc_fft(int n, int dir, const double* in, double* out) {
   }
 #undef HC_CASE
   for (int i = 0; i < n; ++i) {
-    out[2 * i] = buf[i].re;
-    out[2 * i + 1] = buf[i].im;
+    out[2 * i] = buf[lslot<true>(i, 1)].re;
+    out[2 * i + 1] = buf[lslot<true>(i, 1)].im;
   }
   return 0;
 }

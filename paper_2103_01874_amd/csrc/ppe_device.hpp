@@ -137,12 +137,23 @@ PPE_HD void dft(cplx<T>* v) {
   else if constexpr (R == 8) dft8<DIR>(v);
 }
 
+// LDS slot of element n of a transform.  Rows (es == 1) are padded with one
+// slot per 8 elements: the first Stockham stages write with a stride of R
+// elements, which without padding puts every lane of a wavefront on the same
+// LDS banks.  Columns (es > 1, several transforms side by side) are unpadded.
+template <bool PAD>
+PPE_HD int lslot(int n, int es) {
+  return PAD ? n + (n >> 3) : n * es;
+}
+// Slots a padded row of n elements occupies.
+PPE_HD int padded_len(int n) { return n + (n >> 3) + 1; }
+
 // One Stockham stage, split into its read and write halves.
-//   element n of the transform lives at buf[n * es]
+//   element n of the transform lives at buf[lslot(n, es)]
 //   butterfly j in [0, n/R): inputs j + r n/R, twiddle exp(DIR 2 pi i r (j mod Ns)/(Ns R)),
 //   outputs (j / Ns) Ns R + (j mod Ns) + r Ns.
 // Thread t owns butterflies j = t + tc q, q in [0, E/R).
-template <int E, int R, typename T, typename BufT>
+template <int E, int R, bool PAD, typename T, typename BufT>
 PPE_HD void stage_read(const BufT* buf, int es, int t, const FftDev& f, cplx<T>* v) {
   constexpr int NB = E / R;
   const int nr = f.n / R;
@@ -151,13 +162,13 @@ PPE_HD void stage_read(const BufT* buf, int es, int t, const FftDev& f, cplx<T>*
     const int j = t + f.tc * q;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const BufT x = buf[(j + r * nr) * es];
+      const BufT x = buf[lslot<PAD>(j + r * nr, es)];
       v[q * R + r] = mk(T(x.re), T(x.im));
     }
   }
 }
 
-template <int E, int R, int DIR, typename T, typename BufT>
+template <int E, int R, int DIR, bool PAD, typename T, typename BufT>
 PPE_HD void stage_write(BufT* buf, int es, int t, int ns, const FftDev& f, cplx<T>* v) {
   constexpr int NB = E / R;
   const int span = ns * R;
@@ -184,7 +195,7 @@ PPE_HD void stage_write(BufT* buf, int es, int t, int ns, const FftDev& f, cplx<
       BufT o;
       o.re = v[q * R + r].re;
       o.im = v[q * R + r].im;
-      buf[(base + r * ns) * es] = o;
+      buf[lslot<PAD>(base + r * ns, es)] = o;
     }
   }
 }
@@ -192,7 +203,7 @@ PPE_HD void stage_write(BufT* buf, int es, int t, int ns, const FftDev& f, cplx<
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
 // Whole transform in LDS.  Every thread of the block must call this (it
 // contains barriers); threads with active == false only join the barriers.
-template <int E, int DIR, typename T, typename BufT>
+template <int E, int DIR, bool PAD, typename T, typename BufT>
 __device__ __forceinline__ void fft_lds(BufT* buf, int es, int t, bool active, const FftDev& f) {
   int ns = 1;
   for (int s = 0; s < f.nst; ++s) {
@@ -200,27 +211,27 @@ __device__ __forceinline__ void fft_lds(BufT* buf, int es, int t, bool active, c
     cplx<T> v[E];
     if (R == 8) {
       if constexpr (E % 8 == 0) {
-        if (active) stage_read<E, 8, T>(buf, es, t, f, v);
+        if (active) stage_read<E, 8, PAD, T>(buf, es, t, f, v);
         __syncthreads();
-        if (active) stage_write<E, 8, DIR, T>(buf, es, t, ns, f, v);
+        if (active) stage_write<E, 8, DIR, PAD, T>(buf, es, t, ns, f, v);
       }
     } else if (R == 4) {
       if constexpr (E % 4 == 0) {
-        if (active) stage_read<E, 4, T>(buf, es, t, f, v);
+        if (active) stage_read<E, 4, PAD, T>(buf, es, t, f, v);
         __syncthreads();
-        if (active) stage_write<E, 4, DIR, T>(buf, es, t, ns, f, v);
+        if (active) stage_write<E, 4, DIR, PAD, T>(buf, es, t, ns, f, v);
       }
     } else if (R == 3) {
       if constexpr (E % 3 == 0) {
-        if (active) stage_read<E, 3, T>(buf, es, t, f, v);
+        if (active) stage_read<E, 3, PAD, T>(buf, es, t, f, v);
         __syncthreads();
-        if (active) stage_write<E, 3, DIR, T>(buf, es, t, ns, f, v);
+        if (active) stage_write<E, 3, DIR, PAD, T>(buf, es, t, ns, f, v);
       }
     } else {
       if constexpr (E % 2 == 0) {
-        if (active) stage_read<E, 2, T>(buf, es, t, f, v);
+        if (active) stage_read<E, 2, PAD, T>(buf, es, t, f, v);
         __syncthreads();
-        if (active) stage_write<E, 2, DIR, T>(buf, es, t, ns, f, v);
+        if (active) stage_write<E, 2, DIR, PAD, T>(buf, es, t, ns, f, v);
       }
     }
     __syncthreads();

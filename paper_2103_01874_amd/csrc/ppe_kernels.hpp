@@ -78,7 +78,6 @@ struct Work {
   double* scal;         // [inst][kNScal]
   double* partial;      // [inst][pstride] per-block partial sums
   long long pstride;    // doubles of partials per instance
-  unsigned* counter;    // [inst][8]
   const double* lamx;   // [hx]  lam_x(kx)
   const double* lamz;   // [nz]  lam_z(kz)
   int inst0;            // first instance of this launch in the workspace

@@ -18,6 +18,7 @@
 #include "../../include/ppe.h"
 #include "ppe_kernels.hpp"
 #include "ppe_kernels.hip.inc"
+#include "ppe_stencil.hip.inc"
 #include "ppe_plan_util.hpp"
 
 using namespace ppe;
@@ -55,6 +56,11 @@ struct ppe_plan_s {
   int txs = 1, pch = 1;  // systems per block, chunks per system (tri)
   int mc = 16;           // register rows per chunk (template of k_tri)
   size_t lds_x = 0, lds_z = 0, lds_t = 0;
+  March march;             // z-marching stencil tiles
+  int march_grid = 0;      // blocks per instance of a marching kernel
+  int npt = 0;             // points per tile plane
+  int ppt = 1;             // points per thread per plane (template of the marching kernels)
+  double* r64 = nullptr;   // refinement residual (mixed only)
   long long pstride = 0;
   // device memory
   void* spec = nullptr;
@@ -63,7 +69,6 @@ struct ppe_plan_s {
   double* colsum = nullptr;
   double* scal = nullptr;
   double* partial = nullptr;
-  unsigned* counter = nullptr;
   double* lamx = nullptr;
   double* lamz = nullptr;
   size_t bytes = 0;
@@ -107,9 +112,10 @@ bool shape_plan(ppe_plan_s* p) {
   // x kernels: RP row pairs of tc threads
   const int tcx = p->fx.tc;
   if (tcx > 512) return false;
+  const size_t plen = (size_t)padded_len(d.nx);
   p->rp = std::max(1, 256 / tcx);
-  while (p->rp > 1 && ((size_t)p->rp * d.nx * 16 + (size_t)p->rp * tcx * 8 > 65536 || p->rp * tcx > 512)) p->rp /= 2;
-  p->lds_x = (size_t)p->rp * d.nx * 16 + (size_t)p->rp * tcx * 8;
+  while (p->rp > 1 && ((size_t)p->rp * plen * 16 + (size_t)p->rp * tcx * 8 > 65536 || p->rp * tcx > 512)) p->rp /= 2;
+  p->lds_x = (size_t)p->rp * plen * 16 + (size_t)p->rp * tcx * 8;
   // z FFT: TX columns of tc threads
   const int tcz = p->fz.tc;
   if (tcz > 512) return false;
@@ -128,11 +134,26 @@ bool shape_plan(ppe_plan_s* p) {
   p->mc = mmax <= 4 ? 4 : (mmax <= 8 ? 8 : 16);
   p->lds_t = std::max((size_t)p->txs * 2 * P * sizeof(RedRow<double>), (size_t)p->txs * P * 8);
   if (p->lds_x > 65536 || p->lds_z > 65536 || p->lds_t > 65536) return false;
+  // z-marching stencils: TJ full rows per tile, KC planes per chunk
+  March& M = p->march;
+  M.tj = std::max(1, std::min(512 / std::max(1, d.nx), d.ny));
+  if ((long long)M.tj * d.nx > kMarchThreads * kMaxPPT) return false;
+  M.ntj = (d.ny + M.tj - 1) / M.tj;
+  int nkc = std::max(1, (2048 + M.ntj - 1) / M.ntj);
+  nkc = std::min(nkc, std::max(1, d.nz / 2));
+  M.kc = (d.nz + nkc - 1) / nkc;
+  M.nkc = (d.nz + M.kc - 1) / M.kc;
+  M.nt = M.ntj * M.nkc;
+  M.per_xcd = (M.nt + 7) / 8;
+  p->march_grid = 8 * M.per_xcd;
+  p->npt = M.tj * d.nx;
+  p->ppt = 1;
+  while (p->ppt * kMarchThreads < p->npt) p->ppt *= 2;
+  if ((size_t)4 * p->npt * 8 > 65536) return false;
   // per-instance partial-sum stride: the largest grid.x of a reducing kernel
   const long long nrows = (long long)d.ny * d.nz;
-  const long long npairs = (nrows + 1) / 2;
-  const long long gx = (npairs + p->rp - 1) / p->rp;
-  long long gmax = std::max<long long>(gx, kRedBlocks);
+  const long long xgrid = ((nrows + 1) / 2 + p->rp - 1) / p->rp;  // row-pair kernels (k_c2r writes partials)
+  long long gmax = std::max<long long>(std::max<long long>(p->march_grid, kRedBlocks), xgrid);
   p->pstride = 4 * gmax;
   return true;
 }
@@ -142,12 +163,12 @@ size_t workspace_bytes(const ppe_plan_s* p) {
   const size_t B = (size_t)d.batch;
   size_t s = 0;
   s += B * (size_t)p->g.spec_elems * spec_elem_bytes(&d);
-  if (d.precision == PPE_PREC_MIXED) s += B * (size_t)p->g.npts * 8;
+  s += B * (size_t)p->g.npts * 8;                                       // b64
+  if (d.precision == PPE_PREC_MIXED) s += B * (size_t)p->g.npts * 8;    // r64
   s += B * (size_t)d.ny * d.nz * 8;   // rowsum
   s += B * (size_t)d.ny * 8;          // colsum
   s += B * (size_t)kNScal * 8;        // scalars
   s += B * (size_t)p->pstride * 8;    // partials
-  s += B * 8 * sizeof(unsigned);      // counters
   s += (size_t)(d.nx / 2 + 1) * 8 + (size_t)d.nz * 8;  // eigenvalue tables
   s += (size_t)2 * d.nx * 8 + (size_t)2 * d.nz * 8;    // twiddles
   return s;
@@ -163,11 +184,17 @@ hipError_t dalloc(ppe_plan_s* p, T** ptr, size_t bytes) {
 
 void free_plan(ppe_plan_s* p) {
   if (!p) return;
-  void* ptrs[] = {p->spec, p->b64, p->rowsum, p->colsum, p->scal, p->partial, p->counter,
+  void* ptrs[] = {p->spec, p->b64, p->r64, p->rowsum, p->colsum, p->scal, p->partial,
                   p->lamx, p->lamz, p->fx.tw, p->fz.tw};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
+}
+
+// LDS of a marching kernel holding `fields` row arrays (at least the block's
+// reduction scratch, which reuses the same memory after the march)
+size_t march_lds(const ppe_plan_s* p, int fields) {
+  return (size_t)std::max(fields * p->npt, kMarchThreads) * 8;
 }
 
 template <typename TS>
@@ -180,7 +207,6 @@ Work<TS> make_work(ppe_plan_s* p, int inst0) {
   w.scal = p->scal;
   w.partial = p->partial;
   w.pstride = p->pstride;
-  w.counter = p->counter;
   w.lamx = p->lamx;
   w.lamz = p->lamz;
   w.inst0 = inst0;
@@ -190,6 +216,15 @@ Work<TS> make_work(ppe_plan_s* p, int inst0) {
 // ---------------------------------------------------------------------------
 // E dispatch for the FFT kernels
 // ---------------------------------------------------------------------------
+#define PPE_PPT_SWITCH(PVAL, CALL)                  \
+  switch (PVAL) {                                   \
+    case 1: { constexpr int PPT = 1; CALL; } break; \
+    case 2: { constexpr int PPT = 2; CALL; } break; \
+    case 4: { constexpr int PPT = 4; CALL; } break; \
+    case 8: { constexpr int PPT = 8; CALL; } break; \
+    default: return PPE_ERR_UNSUPPORTED;            \
+  }
+
 #define PPE_E_SWITCH(EVAL, CALL)  \
   switch (EVAL) {                 \
     case 1: { constexpr int E = 1; CALL; } break;   \
@@ -201,6 +236,11 @@ Work<TS> make_work(ppe_plan_s* p, int inst0) {
     case 12: { constexpr int E = 12; CALL; } break; \
     default: return PPE_ERR_UNSUPPORTED;            \
   }
+
+void finish(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb, int nblk, int kind, int check,
+            double tol = 0.0, double* out = nullptr) {
+  k_finish<<<nb, 256, 0, p->stream>>>(tab, p->g, p->scal, p->partial, p->pstride, nblk, inst0, kind, check, tol, out);
+}
 
 template <typename TS>
 ppe_status_t launch_fft_z(ppe_plan_s* p, const Work<TS>& W, int nb, int dir, int check) {
@@ -238,7 +278,7 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   Work<TS> W = make_work<TS>(p, inst0);
   const bool mixed = p->d.precision == PPE_PREC_MIXED;
   const double tol = mixed ? p->d.tol : 0.0;
-  k_prologue<<<1, 64, 0, p->stream>>>(tab, p->scal, p->counter, inst0, nb, tol);
+  k_prologue<<<1, 64, 0, p->stream>>>(tab, p->scal, inst0, nb, tol);
   bool need_min = false;
   for (int i = 0; i < nb; ++i) need_min |= !(tab.in[i].rho0_in > 0.0);
   if (need_min) {
@@ -250,17 +290,25 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   const long long npairs = (nrows + 1) / 2;
   dim3 xgrid((unsigned)((npairs + p->rp - 1) / p->rp), 1, nb);
   dim3 xblock(p->rp * p->fx.tc);
+  dim3 mgrid(p->march_grid, 1, nb);
   FftDev fx = to_dev(p->fx);
-  PPE_E_SWITCH(fx.e, (k_assemble<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, mixed ? 1 : 0)));
+  PPE_PPT_SWITCH(p->ppt, (k_rhs<TS, PPT><<<mgrid, kMarchThreads, march_lds(p, 3), p->stream>>>(tab, g, p->march, W)));
+  finish(p, tab, inst0, nb, p->march_grid, FIN_RHS, 0);
+  PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->b64, p->rp, 0)));
   ppe_status_t st = launch_chain<TS>(p, W, nb, 0);
   if (st != PPE_OK) return st;
   PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 0, 0)));
+  finish(p, tab, inst0, nb, (int)xgrid.x, FIN_C2R, 0);
   if (mixed) {
     for (int it = 0; it < p->d.max_refine; ++it) {
-      PPE_E_SWITCH(fx.e, (k_residual<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp)));
+      PPE_PPT_SWITCH(p->ppt, (k_resid<TS, PPT><<<mgrid, kMarchThreads, march_lds(p, 1), p->stream>>>(
+                                  tab, g, p->march, W, p->r64)));
+      finish(p, tab, inst0, nb, p->march_grid, FIN_RESID, 1);
+      PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->r64, p->rp, 1)));
       st = launch_chain<TS>(p, W, nb, 1);
       if (st != PPE_OK) return st;
       PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1)));
+      finish(p, tab, inst0, nb, (int)xgrid.x, FIN_C2R, 1);
     }
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
@@ -308,12 +356,12 @@ ppe_status_t ppe_plan(const ppe_desc_t* desc, void* stream, ppe_plan_t* out) {
   const size_t B = (size_t)d.batch;
   bool ok = true;
   ok &= dalloc(p, (char**)&p->spec, B * (size_t)p->g.spec_elems * spec_elem_bytes(&d)) == hipSuccess;
-  if (d.precision == PPE_PREC_MIXED) ok &= dalloc(p, &p->b64, B * (size_t)p->g.npts * 8) == hipSuccess;
+  ok &= dalloc(p, &p->b64, B * (size_t)p->g.npts * 8) == hipSuccess;
+  if (d.precision == PPE_PREC_MIXED) ok &= dalloc(p, &p->r64, B * (size_t)p->g.npts * 8) == hipSuccess;
   ok &= dalloc(p, &p->rowsum, B * (size_t)d.ny * d.nz * 8) == hipSuccess;
   ok &= dalloc(p, &p->colsum, B * (size_t)d.ny * 8) == hipSuccess;
   ok &= dalloc(p, &p->scal, B * kNScal * 8) == hipSuccess;
   ok &= dalloc(p, &p->partial, B * (size_t)p->pstride * 8) == hipSuccess;
-  ok &= dalloc(p, &p->counter, B * 8 * sizeof(unsigned)) == hipSuccess;
   ok &= dalloc(p, &p->lamx, (size_t)p->g.hx * 8) == hipSuccess;
   ok &= dalloc(p, &p->lamz, (size_t)d.nz * 8) == hipSuccess;
   ok &= dalloc(p, &p->fx.tw, (size_t)2 * d.nx * 8) == hipSuccess;
@@ -340,7 +388,6 @@ ppe_status_t ppe_plan(const ppe_desc_t* desc, void* stream, ppe_plan_t* out) {
   ok &= hipMemcpy(p->lamz, lz.data(), lz.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
   ok &= hipMemcpy(p->fx.tw, twx.data(), twx.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
   ok &= hipMemcpy(p->fz.tw, twz.data(), twz.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
-  ok &= hipMemset(p->counter, 0, B * 8 * sizeof(unsigned)) == hipSuccess;
   if (!ok) {
     free_plan(p);
     return PPE_ERR_DEVICE;
@@ -438,9 +485,9 @@ ppe_status_t ppe_correct(ppe_plan_t p, const double* dt, const double* const* us
       q.info = info + i0 + i;
       q.dt = dt[i0 + i];
     }
-    const long long blocks = std::min<long long>((g.npts + 255) / 256, kRedBlocks);
-    k_correct<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->partial, p->pstride, p->counter, i0,
-                                                                     tol);
+    PPE_PPT_SWITCH(p->ppt, (k_correct<PPT><<<dim3(p->march_grid, 1, nb), kMarchThreads, march_lds(p, 4), p->stream>>>(
+                              tab, g, p->march, p->partial, p->pstride, i0)));
+    finish(p, tab, i0, nb, p->march_grid, FIN_CORRECT, 0, tol);
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
 }
@@ -466,9 +513,11 @@ ppe_status_t ppe_residual(ppe_plan_t p, const double* const* u, const double* co
       q.S = S[i0 + i];
     }
     const long long blocks = std::min<long long>((g.npts + 255) / 256, kRedBlocks);
-    for (int pass = 0; pass < 2; ++pass)
-      k_div_stats<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->partial, p->pstride, p->counter,
+    for (int pass = 0; pass < 2; ++pass) {
+      k_div_stats<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->partial, p->pstride,
                                                                          out + 3 * (size_t)i0, i0, pass);
+      finish(p, tab, i0, nb, (int)blocks, pass == 0 ? FIN_DIV0 : FIN_DIV1, 0, 0.0, out + 3 * (size_t)i0);
+    }
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
 }
