@@ -151,6 +151,23 @@ ppe_status_t ppe_correct(ppe_plan_t plan, const double* dt,
 ppe_status_t ppe_residual(ppe_plan_t plan, const double* const* u, const double* const* v,
                           const double* const* w, const double* const* S, double* out);
 
+/* Per-kernel timing, for measurement tools.  With profiling enabled every
+ * launch the plan makes is bracketed by two HIP events on the plan's stream;
+ * durations are folded into per-kernel totals.  Enabling clears the totals.
+ * The events add a small gap between launches, so leave profiling off for
+ * end-to-end timing. */
+typedef struct {
+  char name[32];           /* kernel family, e.g. "k_correct", "k_fft_z_fwd" */
+  int32_t launches;        /* launches timed since profiling was enabled */
+  double total_ms;         /* sum of their event-to-event durations */
+} ppe_kernel_time_t;
+
+ppe_status_t ppe_plan_profile(ppe_plan_t plan, int32_t enable);
+
+/* Copy up to `cap` per-kernel records into `out` (host memory) and the
+ * number of kernel families into *count.  Waits for the plan's stream. */
+ppe_status_t ppe_plan_profile_read(ppe_plan_t plan, ppe_kernel_time_t* out, int32_t cap, int32_t* count);
+
 /* Library version string (static storage). */
 const char* ppe_version(void);
 

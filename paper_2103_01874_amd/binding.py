@@ -42,7 +42,11 @@ INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("rho0_used", "<f8")
 assert INFO_DTYPE.itemsize == 64
 
 EXPORTS = ["ppe_plan_workspace_bytes", "ppe_plan", "ppe_plan_destroy", "ppe_plan_set_stream", "ppe_solve",
-           "ppe_correct", "ppe_residual", "ppe_version"]
+           "ppe_correct", "ppe_residual", "ppe_plan_profile", "ppe_plan_profile_read", "ppe_version"]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double)]
 
 _lib = None
 
@@ -72,6 +76,11 @@ def load(path: str = LIB_PATH):
     lib.ppe_correct.restype = ctypes.c_int
     lib.ppe_residual.argtypes = [P, PP, PP, PP, PP, P]
     lib.ppe_residual.restype = ctypes.c_int
+    lib.ppe_plan_profile.argtypes = [P, ctypes.c_int32]
+    lib.ppe_plan_profile.restype = ctypes.c_int
+    lib.ppe_plan_profile_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32)]
+    lib.ppe_plan_profile_read.restype = ctypes.c_int
     lib.ppe_version.argtypes = []
     lib.ppe_version.restype = ctypes.c_char_p
     _lib = lib
@@ -139,6 +148,23 @@ class Plan:
     def set_stream(self, stream):
         self.stream = stream
         _check(self.lib.ppe_plan_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)), "ppe_plan_set_stream")
+
+    def profile(self, enable: bool):
+        """Turn per-kernel HIP-event timing on (clearing totals) or off."""
+        _check(self.lib.ppe_plan_profile(self._h, 1 if enable else 0), "ppe_plan_profile")
+
+    def profile_read(self) -> Dict[str, Dict]:
+        """{kernel family: {"launches": n, "total_ms": t, "avg_us": t/n*1e3}} (waits for the stream)."""
+        cap = 64
+        buf = (KernelTime * cap)()
+        n = ctypes.c_int32(0)
+        _check(self.lib.ppe_plan_profile_read(self._h, buf, cap, ctypes.byref(n)), "ppe_plan_profile_read")
+        out = {}
+        for i in range(min(n.value, cap)):
+            k = buf[i]
+            out[k.name.decode()] = {"launches": int(k.launches), "total_ms": float(k.total_ms),
+                                    "avg_us": 1e3 * float(k.total_ms) / max(1, int(k.launches))}
+        return out
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -12,7 +12,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/ppe.h"
@@ -72,6 +74,15 @@ struct ppe_plan_s {
   double* lamx = nullptr;
   double* lamz = nullptr;
   size_t bytes = 0;
+  // opt-in per-kernel timing: HIP events around every launch on the stream
+  bool prof = false;
+  struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<long, double>> acc;  // name -> (launches, total ms)
 };
 
 namespace {
@@ -184,6 +195,11 @@ hipError_t dalloc(ppe_plan_s* p, T** ptr, size_t bytes) {
 
 void free_plan(ppe_plan_s* p) {
   if (!p) return;
+  for (auto& e : p->pending) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   void* ptrs[] = {p->spec, p->b64, p->r64, p->rowsum, p->colsum, p->scal, p->partial,
                   p->lamx, p->lamz, p->fx.tw, p->fz.tw};
   for (void* q : ptrs)
@@ -237,9 +253,56 @@ Work<TS> make_work(ppe_plan_s* p, int inst0) {
     default: return PPE_ERR_UNSUPPORTED;            \
   }
 
+hipEvent_t prof_event(ppe_plan_s* p) {
+  if (!p->pool.empty()) {
+    hipEvent_t e = p->pool.back();
+    p->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Fold recorded event pairs into the per-kernel totals (waits for the stream).
+void prof_collect(ppe_plan_s* p) {
+  if (p->pending.empty()) return;
+  (void)hipStreamSynchronize(p->stream);
+  for (auto& e : p->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      auto& v = p->acc[e.name];
+      v.first += 1;
+      v.second += ms;
+    }
+    p->pool.push_back(e.a);
+    p->pool.push_back(e.b);
+  }
+  p->pending.clear();
+}
+
+// Run a launch statement; with profiling on, bracket it with events.
+#define PPE_TIMED(P, NAME, ...)                                              \
+  do {                                                                       \
+    hipEvent_t ev_a_ = nullptr;                                              \
+    if ((P)->prof) {                                                         \
+      ev_a_ = prof_event(P);                                                 \
+      (void)hipEventRecord(ev_a_, (P)->stream);                              \
+    }                                                                        \
+    __VA_ARGS__;                                                             \
+    if ((P)->prof) {                                                         \
+      hipEvent_t ev_b_ = prof_event(P);                                      \
+      (void)hipEventRecord(ev_b_, (P)->stream);                              \
+      (P)->pending.push_back({NAME, ev_a_, ev_b_});                          \
+      if ((P)->pending.size() > 4096) prof_collect(P);                       \
+    }                                                                        \
+  } while (0)
+
 void finish(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb, int nblk, int kind, int check,
             double tol = 0.0, double* out = nullptr) {
-  k_finish<<<nb, 256, 0, p->stream>>>(tab, p->g, p->scal, p->partial, p->pstride, nblk, inst0, kind, check, tol, out);
+  PPE_TIMED(p, "k_finish",
+            (k_finish<<<nb, 256, 0, p->stream>>>(tab, p->g, p->scal, p->partial, p->pstride, nblk, inst0, kind, check,
+                                                  tol, out)));
 }
 
 template <typename TS>
@@ -249,9 +312,11 @@ ppe_status_t launch_fft_z(ppe_plan_s* p, const Work<TS>& W, int nb, int dir, int
   dim3 block(p->tx * p->fz.tc);
   FftDev fz = to_dev(p->fz);
   if (dir < 0) {
-    PPE_E_SWITCH(fz.e, (k_fft_z<TS, E, -1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check)));
+    PPE_TIMED(p, "k_fft_z_fwd",
+              PPE_E_SWITCH(fz.e, (k_fft_z<TS, E, -1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check))));
   } else {
-    PPE_E_SWITCH(fz.e, (k_fft_z<TS, E, +1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check)));
+    PPE_TIMED(p, "k_fft_z_inv",
+              PPE_E_SWITCH(fz.e, (k_fft_z<TS, E, +1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check))));
   }
   return PPE_OK;
 }
@@ -263,12 +328,14 @@ ppe_status_t launch_chain(ppe_plan_s* p, const Work<TS>& W, int nb, int check) {
   if (st != PPE_OK) return st;
   dim3 tgrid((g.hx + p->txs - 1) / p->txs, g.nz, nb);
   dim3 tblock(p->txs * p->pch);
-  if (p->mc == 4)
-    k_tri<TS, 4><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
-  else if (p->mc == 8)
-    k_tri<TS, 8><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
-  else
-    k_tri<TS, 16><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+  PPE_TIMED(p, "k_tri", {
+    if (p->mc == 4)
+      k_tri<TS, 4><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+    else if (p->mc == 8)
+      k_tri<TS, 8><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+    else
+      k_tri<TS, 16><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+  });
   return launch_fft_z<TS>(p, W, nb, +1, check);
 }
 
@@ -278,13 +345,13 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   Work<TS> W = make_work<TS>(p, inst0);
   const bool mixed = p->d.precision == PPE_PREC_MIXED;
   const double tol = mixed ? p->d.tol : 0.0;
-  k_prologue<<<1, 64, 0, p->stream>>>(tab, p->scal, inst0, nb, tol);
+  PPE_TIMED(p, "k_prologue", (k_prologue<<<1, 64, 0, p->stream>>>(tab, p->scal, inst0, nb, tol)));
   bool need_min = false;
   for (int i = 0; i < nb; ++i) need_min |= !(tab.in[i].rho0_in > 0.0);
   if (need_min) {
     const long long blocks = std::min<long long>((g.npts + 255) / 256, 1024);
-    k_rho_min<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->scal, inst0);
-    k_rho_min_finish<<<1, 64, 0, p->stream>>>(tab, p->scal, inst0, nb);
+    PPE_TIMED(p, "k_rho_min", (k_rho_min<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->scal, inst0)));
+    PPE_TIMED(p, "k_rho_min_finish", (k_rho_min_finish<<<1, 64, 0, p->stream>>>(tab, p->scal, inst0, nb)));
   }
   const long long nrows = (long long)g.ny * g.nz;
   const long long npairs = (nrows + 1) / 2;
@@ -292,22 +359,28 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   dim3 xblock(p->rp * p->fx.tc);
   dim3 mgrid(p->march_grid, 1, nb);
   FftDev fx = to_dev(p->fx);
-  PPE_PPT_SWITCH(p->ppt, (k_rhs<TS, PPT><<<mgrid, kMarchThreads, march_lds(p, 3), p->stream>>>(tab, g, p->march, W)));
+  PPE_TIMED(p, "k_rhs",
+            PPE_PPT_SWITCH(p->ppt, (k_rhs<TS, PPT><<<mgrid, kMarchThreads, march_lds(p, 3), p->stream>>>(tab, g, p->march, W))));
   finish(p, tab, inst0, nb, p->march_grid, FIN_RHS, 0);
-  PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->b64, p->rp, 0)));
+  PPE_TIMED(p, "k_r2c",
+            PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->b64, p->rp, 0))));
   ppe_status_t st = launch_chain<TS>(p, W, nb, 0);
   if (st != PPE_OK) return st;
-  PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 0, 0)));
+  PPE_TIMED(p, "k_c2r",
+            PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 0, 0))));
   finish(p, tab, inst0, nb, (int)xgrid.x, FIN_C2R, 0);
   if (mixed) {
     for (int it = 0; it < p->d.max_refine; ++it) {
-      PPE_PPT_SWITCH(p->ppt, (k_resid<TS, PPT><<<mgrid, kMarchThreads, march_lds(p, 1), p->stream>>>(
-                                  tab, g, p->march, W, p->r64)));
+      PPE_TIMED(p, "k_resid",
+                PPE_PPT_SWITCH(p->ppt, (k_resid<TS, PPT><<<mgrid, kMarchThreads, march_lds(p, 1), p->stream>>>(
+                                            tab, g, p->march, W, p->r64))));
       finish(p, tab, inst0, nb, p->march_grid, FIN_RESID, 1);
-      PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->r64, p->rp, 1)));
+      PPE_TIMED(p, "k_r2c",
+                PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->r64, p->rp, 1))));
       st = launch_chain<TS>(p, W, nb, 1);
       if (st != PPE_OK) return st;
-      PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1)));
+      PPE_TIMED(p, "k_c2r",
+                PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1))));
       finish(p, tab, inst0, nb, (int)xgrid.x, FIN_C2R, 1);
     }
   }
@@ -485,8 +558,9 @@ ppe_status_t ppe_correct(ppe_plan_t p, const double* dt, const double* const* us
       q.info = info + i0 + i;
       q.dt = dt[i0 + i];
     }
-    PPE_PPT_SWITCH(p->ppt, (k_correct<PPT><<<dim3(p->march_grid, 1, nb), kMarchThreads, march_lds(p, 4), p->stream>>>(
-                              tab, g, p->march, p->partial, p->pstride, i0)));
+    PPE_TIMED(p, "k_correct",
+              PPE_PPT_SWITCH(p->ppt, (k_correct<PPT><<<dim3(p->march_grid, 1, nb), kMarchThreads, march_lds(p, 4),
+                                                       p->stream>>>(tab, g, p->march, p->partial, p->pstride, i0))));
     finish(p, tab, i0, nb, p->march_grid, FIN_CORRECT, 0, tol);
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
@@ -514,12 +588,40 @@ ppe_status_t ppe_residual(ppe_plan_t p, const double* const* u, const double* co
     }
     const long long blocks = std::min<long long>((g.npts + 255) / 256, kRedBlocks);
     for (int pass = 0; pass < 2; ++pass) {
-      k_div_stats<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->partial, p->pstride,
-                                                                         out + 3 * (size_t)i0, i0, pass);
+      PPE_TIMED(p, "k_div_stats",
+                (k_div_stats<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->partial, p->pstride,
+                                                                                    out + 3 * (size_t)i0, i0, pass)));
       finish(p, tab, i0, nb, (int)blocks, pass == 0 ? FIN_DIV0 : FIN_DIV1, 0, 0.0, out + 3 * (size_t)i0);
     }
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
+}
+
+ppe_status_t ppe_plan_profile(ppe_plan_t p, int32_t enable) {
+  if (!p) return PPE_ERR_ARG;
+  if (enable) {
+    prof_collect(p);
+    p->acc.clear();
+  }
+  p->prof = enable != 0;
+  return PPE_OK;
+}
+
+ppe_status_t ppe_plan_profile_read(ppe_plan_t p, ppe_kernel_time_t* out, int32_t cap, int32_t* count) {
+  if (!p || !count || cap < 0 || (cap > 0 && !out)) return PPE_ERR_ARG;
+  prof_collect(p);
+  int n = 0;
+  for (const auto& kv : p->acc) {
+    if (n < cap) {
+      std::memset(out[n].name, 0, sizeof(out[n].name));
+      std::strncpy(out[n].name, kv.first.c_str(), sizeof(out[n].name) - 1);
+      out[n].launches = (int32_t)kv.second.first;
+      out[n].total_ms = kv.second.second;
+    }
+    ++n;
+  }
+  *count = n;
+  return PPE_OK;
 }
 
 const char* ppe_version(void) { return "ppe-mi355x 0.1 (gfx950)"; }

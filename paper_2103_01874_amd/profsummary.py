@@ -1,0 +1,128 @@
+"""Summaries of rocprofv3 databases (rocpd SQLite) for the profiles/ folder.
+
+  python -m paper_2103_01874_amd.profsummary trace  DB  --cmd "..."  > profiles/<name>.txt
+  python -m paper_2103_01874_amd.profsummary counters --fetch DB1 --write DB2 --workload W \
+         --copy-bytes B --cmd-fetch "..." --cmd-write "..." --out profiles/counters_W.json
+
+`trace` prints per-kernel launch counts and average durations from a
+--kernel-trace run.  `counters` turns FETCH_SIZE and WRITE_SIZE (KiB per
+dispatch, from two separate --pmc runs) into HBM bytes per launch, each scaled
+by what the same counter reads for the plain device copy of known size that
+the benchmark runs with --copy-bytes (a 1 GiB read + 1 GiB write elementwise
+kernel).
+"""
+
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import os
+import re
+import sqlite3
+import sys
+
+
+def _short(name: str) -> str:
+    n = re.sub(r"\(.*", "", name).replace("void ", "").replace("ppe::", "")
+    return n.strip()
+
+
+def family(name: str) -> str:
+    """Kernel family as the library's event timing names it."""
+    n = _short(name)
+    if n.startswith("k_fft_z"):
+        return "k_fft_z_fwd" if ", -1>" in n else "k_fft_z_inv"
+    return re.sub(r"<.*", "", n)
+
+
+def trace_stats(db_path: str):
+    db = sqlite3.connect(db_path)
+    agg = collections.OrderedDict()
+    for name, start, end in db.execute("select name, start, end from kernels"):
+        a = agg.setdefault(_short(name), [0, 0.0])
+        a[0] += 1
+        a[1] += (end - start) * 1e-3
+    return agg
+
+
+def cmd_trace(args):
+    agg = trace_stats(args.db)
+    tot = sum(v[1] for v in agg.values())
+    print(f"# rocprofv3 kernel trace: {os.path.basename(os.path.dirname(os.path.abspath(args.db)))}")
+    print(f"# command: {args.cmd}")
+    print(f"# {'kernel':<48} {'launches':>8} {'avg_us':>10} {'total_us':>11} {'share':>6}")
+    for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        print(f"  {k[:48]:<48} {n:8d} {t / n:10.2f} {t:11.1f} {100 * t / tot:5.1f}%")
+
+
+def _counter(db_path: str, counter: str):
+    db = sqlite3.connect(db_path)
+    rows = db.execute("select dispatch_id, kernel_name, grid_size, value from counters_collection "
+                      "where counter_name = ? order by dispatch_id", (counter,)).fetchall()
+    return rows
+
+
+def cmd_counters(args):
+    out = {"workload": args.workload, "source_hash": args.source_hash, "copy_bytes": args.copy_bytes,
+           "commands": {"fetch": args.cmd_fetch, "write": args.cmd_write}, "kernels": {}}
+    per = {}
+    factors = {}
+    for counter, path in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+        rows = _counter(path, counter)
+        # calibration: the elementwise copy kernel over copy_bytes (largest grid of that family)
+        cal = [v for _, name, gs, v in rows if "elementwise" in name and gs * 32 >= args.copy_bytes // 8]
+        cal = cal[-3:]
+        if not cal:
+            raise SystemExit(f"no calibration copy found in {path}")
+        kib = sum(cal) / len(cal)
+        factors[counter] = args.copy_bytes / (kib * 1024.0)
+        for _, name, gs, v in rows:
+            fam = family(name)
+            if not fam.startswith("k_"):
+                continue
+            per.setdefault(fam, {}).setdefault(counter, []).append(v)
+    out["factor"] = factors
+    for fam, d in sorted(per.items()):
+        rec = {}
+        tot = 0.0
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            vals = d.get(counter, [])
+            if not vals:
+                continue
+            kib = sum(vals) / len(vals)
+            b = kib * 1024.0 * factors[counter]
+            rec[counter.lower() + "_kib_per_dispatch"] = kib
+            rec[counter.split("_")[0].lower() + "_bytes_per_launch"] = b
+            tot += b
+        rec["hbm_bytes_per_launch"] = tot
+        out["kernels"][fam] = rec
+    with open(args.out, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1, sort_keys=True))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--fetch", required=True)
+    c.add_argument("--write", required=True)
+    c.add_argument("--workload", required=True)
+    c.add_argument("--copy-bytes", type=int, required=True)
+    c.add_argument("--source-hash", required=True)
+    c.add_argument("--cmd-fetch", required=True)
+    c.add_argument("--cmd-write", required=True)
+    c.add_argument("--out", required=True)
+    args = ap.parse_args(argv)
+    if args.cmd_name == "trace":
+        cmd_trace(args)
+    else:
+        cmd_counters(args)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
