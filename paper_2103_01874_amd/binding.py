@@ -58,6 +58,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise PPEError(f"{path} is not built; run `python -m paper_2103_01874_amd.build`")
+    # torch first: its bundled HIP runtime (same soname) must be the one the
+    # library binds to, or torch and the library would run on two runtimes
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     PP = ctypes.POINTER(ctypes.c_void_p)

@@ -76,7 +76,12 @@ void run_tri(int ny, int P, double s, int zero, const double* rhs, double* x) {
     red[2 * p] = f;
     red[2 * p + 1] = l;
   }
-  red_thomas(red.data(), 2 * P);
+  const int n2 = 2 * P;
+  red_twisted_sweep(red.data(), n2, 0, 1);
+  red_twisted_sweep(red.data(), n2, 1, 1);
+  red_twisted_meet(red.data(), n2, 1);
+  red_twisted_subst(red.data(), n2, 0, 1);
+  red_twisted_subst(red.data(), n2, 1, 1);
   for (int p = 0; p < P; ++p) {
     const cplx<double> xf = red[2 * p].d;
     const cplx<double> xl = red[2 * p + 1].d;

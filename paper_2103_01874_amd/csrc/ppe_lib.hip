@@ -11,13 +11,14 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
 #include <string>
 #include <vector>
 
-#include "../../include/ppe.h"
+#include "ppe.h"
 #include "ppe_kernels.hpp"
 #include "ppe_kernels.hip.inc"
 #include "ppe_stencil.hip.inc"
@@ -58,10 +59,13 @@ struct ppe_plan_s {
   int txs = 1, pch = 1;  // systems per block, chunks per system (tri)
   int mc = 16;           // register rows per chunk (template of k_tri)
   size_t lds_x = 0, lds_z = 0, lds_t = 0;
-  March march;             // z-marching stencil tiles
-  int march_grid = 0;      // blocks per instance of a marching kernel
-  int npt = 0;             // points per tile plane
-  int ppt = 1;             // points per thread per plane (template of the marching kernels)
+  // z-marching stencil tiles, one shape per kernel
+  struct MarchCfg {
+    March m;
+    int grid = 0;    // blocks per instance
+    int ppt = 1;     // interior points per thread per plane (kernel template)
+    int tslots = 0;  // LDS slots of a tile plane with its halo ring
+  } mrhs, mcor, mres;
   double* r64 = nullptr;   // refinement residual (mixed only)
   long long pstride = 0;
   // device memory
@@ -87,6 +91,14 @@ struct ppe_plan_s {
 
 namespace {
 
+// Launch-shape overrides for tuning sweeps (PPE_TUNE_* environment variables;
+// unset = the built-in choice).  They change launch shapes only, never the
+// arithmetic.
+int tune_env(const char* name) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : 0;
+}
+
 bool desc_ok(const ppe_desc_t* d) {
   if (!d) return false;
   if (d->nx < 1 || d->nz < 1 || d->ny < 2) return false;
@@ -101,6 +113,41 @@ bool desc_ok(const ppe_desc_t* d) {
 
 size_t spec_elem_bytes(const ppe_desc_t* d) {
   return d->precision == PPE_PREC_FP64 ? 2 * sizeof(double) : 2 * sizeof(float);
+}
+
+// Tile of a marching stencil kernel: TXT = nx when nx <= 128, else the
+// largest divisor of nx up to 128; TJ rows so that a tile plane has about
+// `points` interior cells; KC planes per chunk so that an instance gets about
+// 2048 blocks.
+bool march_shape(const ppe_desc_t& d, int points, const char* env, ppe_plan_s::MarchCfg& c) {
+  March& M = c.m;
+  M.txt = d.nx;
+  if (M.txt > 128) {
+    M.txt = 1;
+    for (int q = 128; q >= 1; --q)
+      if (d.nx % q == 0) {
+        M.txt = q;
+        break;
+      }
+  }
+  M.tj = std::max(1, std::min(points / M.txt, d.ny));
+  if (tune_env(env) > 0) M.tj = std::max(1, std::min(tune_env(env), d.ny));
+  if ((long long)M.tj * M.txt > kMarchThreads * kMaxPPT) return false;
+  M.ntx = d.nx / M.txt;
+  M.ntj = (d.ny + M.tj - 1) / M.tj;
+  const int target = tune_env("PPE_TUNE_MARCH_BLOCKS") > 0 ? tune_env("PPE_TUNE_MARCH_BLOCKS") : 2048;
+  int nkc = std::max(1, (target + M.ntx * M.ntj - 1) / (M.ntx * M.ntj));
+  nkc = std::min(nkc, std::max(1, d.nz / 2));
+  M.kc = (d.nz + nkc - 1) / nkc;
+  M.nkc = (d.nz + M.kc - 1) / M.kc;
+  M.nt = M.ntx * M.ntj * M.nkc;
+  M.per_xcd = (M.nt + 7) / 8;
+  c.grid = 8 * M.per_xcd;
+  const int npt = M.txt * M.tj;
+  c.ppt = 1;
+  while (c.ppt * kMarchThreads < npt) c.ppt *= 2;
+  c.tslots = (M.txt + 2) * (M.tj + 2);
+  return true;
 }
 
 // Launch shapes and workspace sizes; fills p (no allocation).
@@ -131,6 +178,7 @@ bool shape_plan(ppe_plan_s* p) {
   const int tcz = p->fz.tc;
   if (tcz > 512) return false;
   p->tx = std::max(1, std::min(16, 512 / tcz));
+  if (tune_env("PPE_TUNE_TX") > 0) p->tx = std::min(16, tune_env("PPE_TUNE_TX"));
   while (p->tx > 1 && ((size_t)d.nz * p->tx * 16 > 65536 || p->tx * tcz > 512)) p->tx /= 2;
   p->lds_z = std::max((size_t)d.nz * p->tx * 16, (size_t)p->tx * tcz * 8);
   // tri: P chunks of 2..16 rows, TXS systems per block
@@ -145,26 +193,17 @@ bool shape_plan(ppe_plan_s* p) {
   p->mc = mmax <= 4 ? 4 : (mmax <= 8 ? 8 : 16);
   p->lds_t = std::max((size_t)p->txs * 2 * P * sizeof(RedRow<double>), (size_t)p->txs * P * 8);
   if (p->lds_x > 65536 || p->lds_z > 65536 || p->lds_t > 65536) return false;
-  // z-marching stencils: TJ full rows per tile, KC planes per chunk
-  March& M = p->march;
-  M.tj = std::max(1, std::min(512 / std::max(1, d.nx), d.ny));
-  if ((long long)M.tj * d.nx > kMarchThreads * kMaxPPT) return false;
-  M.ntj = (d.ny + M.tj - 1) / M.tj;
-  int nkc = std::max(1, (2048 + M.ntj - 1) / M.ntj);
-  nkc = std::min(nkc, std::max(1, d.nz / 2));
-  M.kc = (d.nz + nkc - 1) / nkc;
-  M.nkc = (d.nz + M.kc - 1) / M.kc;
-  M.nt = M.ntj * M.nkc;
-  M.per_xcd = (M.nt + 7) / 8;
-  p->march_grid = 8 * M.per_xcd;
-  p->npt = M.tj * d.nx;
-  p->ppt = 1;
-  while (p->ppt * kMarchThreads < p->npt) p->ppt *= 2;
-  if ((size_t)4 * p->npt * 8 > 65536) return false;
+  // z-marching stencils: TXT x TJ tiles (TXT a divisor of nx, <= 128), KC planes
+  // per chunk; the tile height per kernel trades halo traffic against registers
+  if (!march_shape(d, 256, "PPE_TUNE_TJ_RHS", p->mrhs) || !march_shape(d, 256, "PPE_TUNE_TJ_COR", p->mcor) ||
+      !march_shape(d, 512, "PPE_TUNE_TJ_RES", p->mres))
+    return false;
+  if ((size_t)3 * p->mcor.tslots * 8 > 65536) return false;
   // per-instance partial-sum stride: the largest grid.x of a reducing kernel
   const long long nrows = (long long)d.ny * d.nz;
   const long long xgrid = ((nrows + 1) / 2 + p->rp - 1) / p->rp;  // row-pair kernels (k_c2r writes partials)
-  long long gmax = std::max<long long>(std::max<long long>(p->march_grid, kRedBlocks), xgrid);
+  long long gmax = std::max<long long>(kRedBlocks, xgrid);
+  gmax = std::max<long long>(gmax, std::max(p->mrhs.grid, std::max(p->mcor.grid, p->mres.grid)));
   p->pstride = 4 * gmax;
   return true;
 }
@@ -209,8 +248,8 @@ void free_plan(ppe_plan_s* p) {
 
 // LDS of a marching kernel holding `fields` row arrays (at least the block's
 // reduction scratch, which reuses the same memory after the march)
-size_t march_lds(const ppe_plan_s* p, int fields) {
-  return (size_t)std::max(fields * p->npt, kMarchThreads) * 8;
+size_t march_lds(const ppe_plan_s::MarchCfg& c, int fields) {
+  return (size_t)std::max(fields * c.tslots, kMarchThreads) * 8;
 }
 
 template <typename TS>
@@ -237,7 +276,6 @@ Work<TS> make_work(ppe_plan_s* p, int inst0) {
     case 1: { constexpr int PPT = 1; CALL; } break; \
     case 2: { constexpr int PPT = 2; CALL; } break; \
     case 4: { constexpr int PPT = 4; CALL; } break; \
-    case 8: { constexpr int PPT = 8; CALL; } break; \
     default: return PPE_ERR_UNSUPPORTED;            \
   }
 
@@ -301,7 +339,7 @@ void prof_collect(ppe_plan_s* p) {
 void finish(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb, int nblk, int kind, int check,
             double tol = 0.0, double* out = nullptr) {
   PPE_TIMED(p, "k_finish",
-            (k_finish<<<nb, 256, 0, p->stream>>>(tab, p->g, p->scal, p->partial, p->pstride, nblk, inst0, kind, check,
+            (k_finish<<<nb, kFinishThreads, 0, p->stream>>>(tab, p->g, p->scal, p->partial, p->pstride, nblk, inst0, kind, check,
                                                   tol, out)));
 }
 
@@ -357,31 +395,30 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   const long long npairs = (nrows + 1) / 2;
   dim3 xgrid((unsigned)((npairs + p->rp - 1) / p->rp), 1, nb);
   dim3 xblock(p->rp * p->fx.tc);
-  dim3 mgrid(p->march_grid, 1, nb);
   FftDev fx = to_dev(p->fx);
   PPE_TIMED(p, "k_rhs",
-            PPE_PPT_SWITCH(p->ppt, (k_rhs<TS, PPT><<<mgrid, kMarchThreads, march_lds(p, 3), p->stream>>>(tab, g, p->march, W))));
-  finish(p, tab, inst0, nb, p->march_grid, FIN_RHS, 0);
+            PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads, march_lds(p->mrhs, 2),
+                                                        p->stream>>>(tab, g, p->mrhs.m, W))));
+  finish(p, tab, inst0, nb, p->mrhs.grid, FIN_RHS, 0);
   PPE_TIMED(p, "k_r2c",
             PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->b64, p->rp, 0))));
   ppe_status_t st = launch_chain<TS>(p, W, nb, 0);
   if (st != PPE_OK) return st;
   PPE_TIMED(p, "k_c2r",
             PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 0, 0))));
-  finish(p, tab, inst0, nb, (int)xgrid.x, FIN_C2R, 0);
   if (mixed) {
     for (int it = 0; it < p->d.max_refine; ++it) {
       PPE_TIMED(p, "k_resid",
-                PPE_PPT_SWITCH(p->ppt, (k_resid<TS, PPT><<<mgrid, kMarchThreads, march_lds(p, 1), p->stream>>>(
-                                            tab, g, p->march, W, p->r64))));
-      finish(p, tab, inst0, nb, p->march_grid, FIN_RESID, 1);
+                PPE_PPT_SWITCH(p->mres.ppt, (k_resid<TS, PPT><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
+                                                                march_lds(p->mres, 1), p->stream>>>(tab, g, p->mres.m, W,
+                                                                                                    p->r64))));
+      finish(p, tab, inst0, nb, p->mres.grid, FIN_RESID, 1);
       PPE_TIMED(p, "k_r2c",
                 PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->r64, p->rp, 1))));
       st = launch_chain<TS>(p, W, nb, 1);
       if (st != PPE_OK) return st;
       PPE_TIMED(p, "k_c2r",
                 PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1))));
-      finish(p, tab, inst0, nb, (int)xgrid.x, FIN_C2R, 1);
     }
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
@@ -559,9 +596,10 @@ ppe_status_t ppe_correct(ppe_plan_t p, const double* dt, const double* const* us
       q.dt = dt[i0 + i];
     }
     PPE_TIMED(p, "k_correct",
-              PPE_PPT_SWITCH(p->ppt, (k_correct<PPT><<<dim3(p->march_grid, 1, nb), kMarchThreads, march_lds(p, 4),
-                                                       p->stream>>>(tab, g, p->march, p->partial, p->pstride, i0))));
-    finish(p, tab, i0, nb, p->march_grid, FIN_CORRECT, 0, tol);
+              PPE_PPT_SWITCH(p->mcor.ppt, (k_correct<PPT><<<dim3(p->mcor.grid, 1, nb), kMarchThreads,
+                                                            march_lds(p->mcor, 3), p->stream>>>(
+                                               tab, g, p->mcor.m, p->partial, p->pstride, i0))));
+    finish(p, tab, i0, nb, p->mcor.grid, FIN_CORRECT, 0, tol);
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
 }
