@@ -252,7 +252,7 @@ def to_device(problem, device="cuda"):
             for k in ("us", "vs", "ws", "rho", "pn", "pnm1", "S")}
 
 
-def step(plan: Plan, fields: List[Dict], rho0, dt, outputs: Optional[List[Dict]] = None):
+def step(plan: Plan, fields: List[Dict], rho0, dt, outputs: Optional[List[Dict]] = None, info=None):
     """solve + correct for a batch of field dicts; returns (outputs, info tensor)."""
     torch = plan._torch
     if outputs is None:
@@ -260,7 +260,7 @@ def step(plan: Plan, fields: List[Dict], rho0, dt, outputs: Optional[List[Dict]]
                     "v": torch.empty_like(f["vs"]), "w": torch.empty_like(f["ws"])} for f in fields]
     g = lambda k: [f[k] for f in fields]
     o = lambda k: [x[k] for x in outputs]
-    info = plan.solve(rho0, dt, g("us"), g("vs"), g("ws"), g("rho"), g("pn"), g("pnm1"), g("S"), o("p"))
+    info = plan.solve(rho0, dt, g("us"), g("vs"), g("ws"), g("rho"), g("pn"), g("pnm1"), g("S"), o("p"), info)
     plan.correct(dt, g("us"), g("vs"), g("ws"), g("rho"), g("pn"), g("pnm1"), o("p"), g("S"), o("u"), o("v"),
                  o("w"), info)
     return outputs, info
