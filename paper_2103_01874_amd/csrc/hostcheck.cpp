@@ -23,9 +23,13 @@ void run_fft(const HostFft& h, const std::vector<double>& tw, cplx<double>* buf)
   f.e = h.e;
   f.tc = h.tc;
   f.nst = h.nst;
-  for (int s = 0; s < kMaxStages; ++s) f.radix[s] = h.radix[s];
+  for (int s = 0; s < kMaxStages; ++s) {
+    f.radix[s] = h.radix[s];
+    f.ns[s] = h.ns[s];
+    f.tstep[s] = h.tstep[s];
+    f.inv_ns[s] = h.inv_ns[s];
+  }
   f.tw = tw.data();
-  int ns = 1;
   std::vector<cplx<double>> regs((size_t)f.tc * E);
   for (int s = 0; s < f.nst; ++s) {
     const int R = f.radix[s];
@@ -39,12 +43,11 @@ void run_fft(const HostFft& h, const std::vector<double>& tw, cplx<double>* buf)
     }
     for (int t = 0; t < f.tc; ++t) {
       cplx<double>* v = &regs[(size_t)t * E];
-      if constexpr (E % 8 == 0) if (R == 8) stage_write<E, 8, DIR, PAD, double>(buf, 1, t, ns, f, v);
-      if constexpr (E % 4 == 0) if (R == 4) stage_write<E, 4, DIR, PAD, double>(buf, 1, t, ns, f, v);
-      if constexpr (E % 3 == 0) if (R == 3) stage_write<E, 3, DIR, PAD, double>(buf, 1, t, ns, f, v);
-      if constexpr (E % 2 == 0) if (R == 2) stage_write<E, 2, DIR, PAD, double>(buf, 1, t, ns, f, v);
+      if constexpr (E % 8 == 0) if (R == 8) stage_write<E, 8, DIR, PAD, double>(buf, 1, t, s, f, f.tw, v);
+      if constexpr (E % 4 == 0) if (R == 4) stage_write<E, 4, DIR, PAD, double>(buf, 1, t, s, f, f.tw, v);
+      if constexpr (E % 3 == 0) if (R == 3) stage_write<E, 3, DIR, PAD, double>(buf, 1, t, s, f, f.tw, v);
+      if constexpr (E % 2 == 0) if (R == 2) stage_write<E, 2, DIR, PAD, double>(buf, 1, t, s, f, f.tw, v);
     }
-    ns *= R;
   }
 }
 

@@ -50,6 +50,23 @@ PPE_HD cplx<T> mul_i(cplx<T> a) {
   return DIR < 0 ? mk(a.im, -a.re) : mk(-a.im, a.re);
 }
 
+// 1/x for finite non-zero x: the hardware reciprocal estimate refined by two
+// Newton steps (each doubles the correct bits), accurate to about one unit in
+// the last place and much shorter than a correctly rounded division, which
+// matters inside the sequential sweeps.  The host build divides.
+PPE_HD double rcp_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, y, 1.0);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-x, y, 1.0);
+  return __builtin_fma(y, e, y);
+#else
+  return 1.0 / x;
+#endif
+}
+PPE_HD float rcp_nr(float x) { return 1.0f / x; }
+
 // ---------------------------------------------------------------------------
 // FFT plan as seen by a kernel (passed by value)
 // ---------------------------------------------------------------------------
@@ -61,7 +78,11 @@ struct FftDev {
   int tc;                  // threads per transform = n / e
   int nst;                 // number of stages
   int radix[kMaxStages];   // radix of each stage
+  int ns[kMaxStages];      // length of the sub-transforms done before the stage
+  int tstep[kMaxStages];   // twiddle index step n / (ns * radix)
+  float inv_ns[kMaxStages];  // 1 / ns (quotient estimate, corrected exactly)
   const double* tw;        // 2*n doubles: W_n^t = exp(-2 pi i t / n), t = 0..n-1
+                           // (global table; kernels stage a copy in LDS)
 };
 
 // Small DFTs on registers.  DIR = -1 forward (exp(-i...)), +1 inverse.
@@ -168,25 +189,58 @@ PPE_HD void stage_read(const BufT* buf, int es, int t, const FftDev& f, cplx<T>*
   }
 }
 
+// j / ns and j mod ns for 0 <= j < 2^24 from a float quotient estimate,
+// corrected to the exact integers.
+PPE_HD void fast_divmod(int j, int ns, float inv_ns, int& q, int& r) {
+  q = (int)((float)j * inv_ns);
+  r = j - q * ns;
+  if (r < 0) {
+    q -= 1;
+    r += ns;
+  } else if (r >= ns) {
+    q += 1;
+    r -= ns;
+  }
+}
+
+template <int DIR, typename T>
+PPE_HD cplx<T> tw_load(const double* tw, int ti) {
+  return mk(T(tw[2 * ti]), DIR > 0 ? T(-tw[2 * ti + 1]) : T(tw[2 * ti + 1]));
+}
+
+// Stage twiddles w^r, r = 1..R-1, of w = W_n^{jm tstep}: w, w^2 (and w^4 for
+// radix 8) come from the table, the others are products of those (at most
+// two roundings more than a table value).
+template <int R, int DIR, typename T>
+PPE_HD void stage_twiddles_of(const double* tw, int base, cplx<T>* w) {
+  w[1] = tw_load<DIR, T>(tw, base);
+  if constexpr (R >= 3) w[2] = tw_load<DIR, T>(tw, 2 * base);
+  if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
+  if constexpr (R == 8) {
+    w[3] = cmul(w[1], w[2]);
+    w[4] = tw_load<DIR, T>(tw, 4 * base);
+    w[5] = cmul(w[1], w[4]);
+    w[6] = cmul(w[2], w[4]);
+    w[7] = cmul(w[3], w[4]);
+  }
+}
+
 template <int E, int R, int DIR, bool PAD, typename T, typename BufT>
-PPE_HD void stage_write(BufT* buf, int es, int t, int ns, const FftDev& f, cplx<T>* v) {
+PPE_HD void stage_write(BufT* buf, int es, int t, int st, const FftDev& f, const double* tw, cplx<T>* v) {
   constexpr int NB = E / R;
+  const int ns = f.ns[st];
   const int span = ns * R;
-  const int tstep = f.n / span;  // twiddle index step: W_n^{r (j mod ns) n/(ns R)}
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int j = t + f.tc * q;
-    const int jm = j % ns;
-    const int jd = j / ns;
+    int jd, jm;
+    fast_divmod(j, ns, f.inv_ns[st], jd, jm);
     if (ns > 1) {
+      // twiddles W_n^{r (j mod ns) n/(ns R)}
+      cplx<T> w[R];
+      stage_twiddles_of<R, DIR, T>(tw, jm * f.tstep[st], w);
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const int ti = r * jm * tstep;
-        T wr = T(f.tw[2 * ti]);
-        T wi = T(f.tw[2 * ti + 1]);
-        if (DIR > 0) wi = -wi;
-        v[q * R + r] = cmul(v[q * R + r], mk(wr, wi));
-      }
+      for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], w[r]);
     }
     dft<R, DIR>(&v[q * R]);
     const int base = jd * span + jm;
@@ -201,11 +255,17 @@ PPE_HD void stage_write(BufT* buf, int es, int t, int ns, const FftDev& f, cplx<
 }
 
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+// Copy the twiddle table of `f` into LDS (all threads of the block; the
+// caller's next barrier publishes it).
+__device__ __forceinline__ void stage_twiddles(double* lds_tw, const FftDev& f) {
+  for (int q = threadIdx.x; q < 2 * f.n; q += blockDim.x) lds_tw[q] = f.tw[q];
+}
+
 // Whole transform in LDS.  Every thread of the block must call this (it
 // contains barriers); threads with active == false only join the barriers.
+// `tw` is the twiddle table, normally the copy a kernel staged in LDS.
 template <int E, int DIR, bool PAD, typename T, typename BufT>
-__device__ __forceinline__ void fft_lds(BufT* buf, int es, int t, bool active, const FftDev& f) {
-  int ns = 1;
+__device__ __forceinline__ void fft_lds(BufT* buf, int es, int t, bool active, const FftDev& f, const double* tw) {
   for (int s = 0; s < f.nst; ++s) {
     const int R = f.radix[s];
     cplx<T> v[E];
@@ -213,29 +273,28 @@ __device__ __forceinline__ void fft_lds(BufT* buf, int es, int t, bool active, c
       if constexpr (E % 8 == 0) {
         if (active) stage_read<E, 8, PAD, T>(buf, es, t, f, v);
         __syncthreads();
-        if (active) stage_write<E, 8, DIR, PAD, T>(buf, es, t, ns, f, v);
+        if (active) stage_write<E, 8, DIR, PAD, T>(buf, es, t, s, f, tw, v);
       }
     } else if (R == 4) {
       if constexpr (E % 4 == 0) {
         if (active) stage_read<E, 4, PAD, T>(buf, es, t, f, v);
         __syncthreads();
-        if (active) stage_write<E, 4, DIR, PAD, T>(buf, es, t, ns, f, v);
+        if (active) stage_write<E, 4, DIR, PAD, T>(buf, es, t, s, f, tw, v);
       }
     } else if (R == 3) {
       if constexpr (E % 3 == 0) {
         if (active) stage_read<E, 3, PAD, T>(buf, es, t, f, v);
         __syncthreads();
-        if (active) stage_write<E, 3, DIR, PAD, T>(buf, es, t, ns, f, v);
+        if (active) stage_write<E, 3, DIR, PAD, T>(buf, es, t, s, f, tw, v);
       }
     } else {
       if constexpr (E % 2 == 0) {
         if (active) stage_read<E, 2, PAD, T>(buf, es, t, f, v);
         __syncthreads();
-        if (active) stage_write<E, 2, DIR, PAD, T>(buf, es, t, ns, f, v);
+        if (active) stage_write<E, 2, DIR, PAD, T>(buf, es, t, s, f, tw, v);
       }
     }
     __syncthreads();
-    ns *= R;
   }
 }
 #endif
@@ -270,7 +329,7 @@ PPE_HD void chunk_eliminate(cplx<T>* r, int m, T s, T* phi, T* psi) {
   for (int i = 0; i < MC - 2; ++i) {
     if (i < ni) {
       if (i > 0) g = s + g * q[i - 1];
-      const T qi = T(1) / (T(1) + g);
+      const T qi = rcp_nr(T(1) + g);
       q[i] = qi;
       const cplx<T> ri = r[i + 1];
       if (i == 0) {
@@ -360,7 +419,7 @@ PPE_HD void red_twisted_sweep(RedRow<T>* rows, int n, int who, int st) {
     for (int i = 0; i < h; ++i) {
       const RedRow<T> r = nxt;
       if (i + 1 < h) nxt = rows[(i + 1) * st];
-      const T inv = T(1) / (r.b - r.a * cp);
+      const T inv = rcp_nr(r.b - r.a * cp);
       cp = r.c * inv;
       dp = mk((r.d.re - r.a * dp.re) * inv, (r.d.im - r.a * dp.im) * inv);
       rows[i * st].c = cp;
@@ -373,7 +432,7 @@ PPE_HD void red_twisted_sweep(RedRow<T>* rows, int n, int who, int st) {
     for (int i = n - 1; i >= h; --i) {
       const RedRow<T> r = nxt;
       if (i - 1 >= h) nxt = rows[(i - 1) * st];
-      const T inv = T(1) / (r.b - r.c * ap);
+      const T inv = rcp_nr(r.b - r.c * ap);
       ap = r.a * inv;
       dp = mk((r.d.re - r.c * dp.re) * inv, (r.d.im - r.c * dp.im) * inv);
       rows[i * st].a = ap;
@@ -389,7 +448,7 @@ PPE_HD void red_twisted_meet(RedRow<T>* rows, int n, int st) {
   const int h = n / 2;
   const T c = rows[(h - 1) * st].c, a = rows[h * st].a;
   const cplx<T> d1 = rows[(h - 1) * st].d, d2 = rows[h * st].d;
-  const T inv = T(1) / (T(1) - c * a);
+  const T inv = rcp_nr(T(1) - c * a);
   const cplx<T> xm = mk((d1.re - c * d2.re) * inv, (d1.im - c * d2.im) * inv);
   rows[(h - 1) * st].d = xm;
   rows[h * st].d = mk(d2.re - a * xm.re, d2.im - a * xm.im);

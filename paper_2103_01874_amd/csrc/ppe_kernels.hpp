@@ -61,12 +61,23 @@ struct PtrTable {
 
 struct Geom {
   int nx, ny, nz, hx;
+  int tws;              // log2 of the spectrum tile width (128-byte tiles of kx)
   long long npts;       // nx*ny*nz
-  long long spec_elems; // nz*ny*hx
+  long long spec_elems; // ntiles * nz * ny * tile width (>= hx * ny * nz)
   double idx, idy, idz; // 1/dx, 1/dy, 1/dz
   double dy2;           // dy^2
   double inv_nxnz;      // 1/(nx*nz)
 };
+
+// Half-spectrum layout: tiles of 2^tws consecutive kx (128 bytes) hold, for
+// every (kz, j), their values contiguously:
+//   [tile][kz][j][kx mod 2^tws]
+// so a y system of one tile is one contiguous run and a z column strides
+// ny * 2^tws values.  `row` = kz * ny + j.
+__host__ __device__ __forceinline__ long long sidx(const Geom& g, int kx, long long row) {
+  const long long t = kx >> g.tws;
+  return ((t * g.nz * g.ny + row) << g.tws) + (kx & ((1 << g.tws) - 1));
+}
 
 // Workspace seen by the kernels (device pointers, per-instance strides).
 template <typename TS>

@@ -37,7 +37,12 @@ FftDev to_dev(const HostFft& h) {
   d.e = h.e;
   d.tc = h.tc;
   d.nst = h.nst;
-  for (int s = 0; s < kMaxStages; ++s) d.radix[s] = h.radix[s];
+  for (int s = 0; s < kMaxStages; ++s) {
+    d.radix[s] = h.radix[s];
+    d.ns[s] = h.ns[s];
+    d.tstep[s] = h.tstep[s];
+    d.inv_ns[s] = h.inv_ns[s];
+  }
   d.tw = h.tw;
   return d;
 }
@@ -119,12 +124,13 @@ size_t spec_elem_bytes(const ppe_desc_t* d) {
 // largest divisor of nx up to 128; TJ rows so that a tile plane has about
 // `points` interior cells; KC planes per chunk so that an instance gets about
 // 2048 blocks.
-bool march_shape(const ppe_desc_t& d, int points, const char* env, ppe_plan_s::MarchCfg& c) {
+bool march_shape(const ppe_desc_t& d, int points, int max_txt, const char* env, ppe_plan_s::MarchCfg& c) {
   March& M = c.m;
+  if (tune_env("PPE_TUNE_TXT") > 0) max_txt = tune_env("PPE_TUNE_TXT");
   M.txt = d.nx;
-  if (M.txt > 128) {
+  if (M.txt > max_txt) {
     M.txt = 1;
-    for (int q = 128; q >= 1; --q)
+    for (int q = max_txt; q >= 1; --q)
       if (d.nx % q == 0) {
         M.txt = q;
         break;
@@ -132,6 +138,7 @@ bool march_shape(const ppe_desc_t& d, int points, const char* env, ppe_plan_s::M
   }
   M.tj = std::max(1, std::min(points / M.txt, d.ny));
   if (tune_env(env) > 0) M.tj = std::max(1, std::min(tune_env(env), d.ny));
+  while (M.tj > 1 && 2 * M.txt + 2 * M.tj > kRingPT * kMarchThreads) --M.tj;
   if ((long long)M.tj * M.txt > kMarchThreads * kMaxPPT) return false;
   M.ntx = d.nx / M.txt;
   M.ntj = (d.ny + M.tj - 1) / M.tj;
@@ -150,8 +157,10 @@ bool march_shape(const ppe_desc_t& d, int points, const char* env, ppe_plan_s::M
   return true;
 }
 
-// Launch shapes and workspace sizes; fills p (no allocation).
-bool shape_plan(ppe_plan_s* p) {
+// Launch shapes and workspace sizes; fills p (no allocation).  `lds_limit`
+// is the largest dynamic LDS a block may use (64 KiB without the per-kernel
+// opt-in; 160 KiB on gfx950 with it).
+bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   const ppe_desc_t& d = p->d;
   if (!fft_factor(d.nx, p->fx) || !fft_factor(d.nz, p->fz)) return false;
   Geom& g = p->g;
@@ -159,8 +168,10 @@ bool shape_plan(ppe_plan_s* p) {
   g.ny = d.ny;
   g.nz = d.nz;
   g.hx = d.nx / 2 + 1;
+  g.tws = d.precision == PPE_PREC_FP64 ? 3 : 4;  // 128-byte kx tiles
   g.npts = (long long)d.nx * d.ny * d.nz;
-  g.spec_elems = (long long)d.nz * d.ny * g.hx;
+  const long long ntile = (g.hx + (1 << g.tws) - 1) >> g.tws;
+  g.spec_elems = (ntile << g.tws) * d.ny * d.nz;
   const double dx = d.lx / d.nx, dy = d.ly / d.ny, dz = d.lz / d.nz;
   g.idx = 1.0 / dx;
   g.idy = 1.0 / dy;
@@ -172,15 +183,17 @@ bool shape_plan(ppe_plan_s* p) {
   if (tcx > 512) return false;
   const size_t plen = (size_t)padded_len(d.nx);
   p->rp = std::max(1, 256 / tcx);
-  while (p->rp > 1 && ((size_t)p->rp * plen * 16 + (size_t)p->rp * tcx * 8 > 65536 || p->rp * tcx > 512)) p->rp /= 2;
-  p->lds_x = (size_t)p->rp * plen * 16 + (size_t)p->rp * tcx * 8;
+  while (p->rp > 1 && ((size_t)p->rp * plen * 16 > 65536 || p->rp * tcx > 512)) p->rp /= 2;
+  p->lds_x = (size_t)p->rp * plen * 16;  // padded rows (twiddles are read from the global table)
   // z FFT: TX columns of tc threads
   const int tcz = p->fz.tc;
   if (tcz > 512) return false;
-  p->tx = std::max(1, std::min(16, 512 / tcz));
-  if (tune_env("PPE_TUNE_TX") > 0) p->tx = std::min(16, tune_env("PPE_TUNE_TX"));
-  while (p->tx > 1 && ((size_t)d.nz * p->tx * 16 > 65536 || p->tx * tcz > 512)) p->tx /= 2;
-  p->lds_z = std::max((size_t)d.nz * p->tx * 16, (size_t)p->tx * tcz * 8);
+  // one 128-byte kx tile per block when LDS allows (TX must divide the tile)
+  p->tx = 1 << g.tws;
+  if (tune_env("PPE_TUNE_TX") > 0) p->tx = std::min(p->tx, tune_env("PPE_TUNE_TX"));
+  while (p->tx > 1 && ((size_t)d.nz * p->tx * 16 + (size_t)d.nz * 16 > lds_limit || p->tx * tcz > 512)) p->tx /= 2;
+  // columns + twiddle table (the plane-sum reduction reuses the column area)
+  p->lds_z = std::max((size_t)d.nz * p->tx * 16, (size_t)p->tx * tcz * 8) + (size_t)d.nz * 16;
   // tri: P chunks of 2..16 rows, TXS systems per block
   int P = (int)std::lround(d.ny / 8.0);
   P = std::max(P, (d.ny + kMaxChunk - 1) / kMaxChunk);
@@ -192,16 +205,16 @@ bool shape_plan(ppe_plan_s* p) {
   const int mmax = (d.ny + P - 1) / P;
   p->mc = mmax <= 4 ? 4 : (mmax <= 8 ? 8 : 16);
   p->lds_t = std::max((size_t)p->txs * 2 * P * sizeof(RedRow<double>), (size_t)p->txs * P * 8);
-  if (p->lds_x > 65536 || p->lds_z > 65536 || p->lds_t > 65536) return false;
+  if (p->lds_x > 65536 || p->lds_z > lds_limit || p->lds_t > 65536) return false;
   // z-marching stencils: TXT x TJ tiles (TXT a divisor of nx, <= 128), KC planes
   // per chunk; the tile height per kernel trades halo traffic against registers
-  if (!march_shape(d, 256, "PPE_TUNE_TJ_RHS", p->mrhs) || !march_shape(d, 256, "PPE_TUNE_TJ_COR", p->mcor) ||
-      !march_shape(d, 512, "PPE_TUNE_TJ_RES", p->mres))
+  if (!march_shape(d, 256, 64, "PPE_TUNE_TJ_RHS", p->mrhs) || !march_shape(d, 256, 64, "PPE_TUNE_TJ_COR", p->mcor) ||
+      !march_shape(d, 512, 128, "PPE_TUNE_TJ_RES", p->mres))
     return false;
   if ((size_t)3 * p->mcor.tslots * 8 > 65536) return false;
   // per-instance partial-sum stride: the largest grid.x of a reducing kernel
   const long long nrows = (long long)d.ny * d.nz;
-  const long long xgrid = ((nrows + 1) / 2 + p->rp - 1) / p->rp;  // row-pair kernels (k_c2r writes partials)
+  const long long xgrid = (nrows + 1) / 2;  // bound on the row-pair grids, whatever the launch shape
   long long gmax = std::max<long long>(kRedBlocks, xgrid);
   gmax = std::max<long long>(gmax, std::max(p->mrhs.grid, std::max(p->mcor.grid, p->mres.grid)));
   p->pstride = 4 * gmax;
@@ -383,10 +396,10 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   Work<TS> W = make_work<TS>(p, inst0);
   const bool mixed = p->d.precision == PPE_PREC_MIXED;
   const double tol = mixed ? p->d.tol : 0.0;
-  PPE_TIMED(p, "k_prologue", (k_prologue<<<1, 64, 0, p->stream>>>(tab, p->scal, inst0, nb, tol)));
   bool need_min = false;
   for (int i = 0; i < nb; ++i) need_min |= !(tab.in[i].rho0_in > 0.0);
   if (need_min) {
+    PPE_TIMED(p, "k_rho_min_init", (k_rho_min_init<<<1, 64, 0, p->stream>>>(p->scal, inst0, nb)));
     const long long blocks = std::min<long long>((g.npts + 255) / 256, 1024);
     PPE_TIMED(p, "k_rho_min", (k_rho_min<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->scal, inst0)));
     PPE_TIMED(p, "k_rho_min_finish", (k_rho_min_finish<<<1, 64, 0, p->stream>>>(tab, p->scal, inst0, nb)));
@@ -399,7 +412,7 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   PPE_TIMED(p, "k_rhs",
             PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads, march_lds(p->mrhs, 2),
                                                         p->stream>>>(tab, g, p->mrhs.m, W))));
-  finish(p, tab, inst0, nb, p->mrhs.grid, FIN_RHS, 0);
+  finish(p, tab, inst0, nb, p->mrhs.grid, FIN_RHS, 0, tol);
   PPE_TIMED(p, "k_r2c",
             PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->b64, p->rp, 0))));
   ppe_status_t st = launch_chain<TS>(p, W, nb, 0);
@@ -433,6 +446,35 @@ bool ptrs_ok(const void* const* a, int n) {
 
 }  // namespace
 
+namespace {
+// Dynamic LDS above 64 KiB must be enabled per kernel (all z-FFT variants).
+template <typename TS, int E>
+hipError_t allow_big_lds_e(int bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_z<TS, E, -1>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_z<TS, E, +1>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+template <typename TS>
+hipError_t allow_big_lds_t(int bytes) {
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = allow_big_lds_e<TS, 1>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, 2>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, 3>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, 4>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, 6>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, 8>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, 12>(bytes);
+  return e;
+}
+hipError_t allow_big_lds(int bytes) {
+  hipError_t e = allow_big_lds_t<double>(bytes);
+  return e == hipSuccess ? allow_big_lds_t<float>(bytes) : e;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -454,11 +496,18 @@ ppe_status_t ppe_plan(const ppe_desc_t* desc, void* stream, ppe_plan_t* out) {
   if (!p) return PPE_ERR_NOMEM;
   p->d = *desc;
   p->stream = reinterpret_cast<hipStream_t>(stream);
-  if (!shape_plan(p)) {
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return PPE_ERR_DEVICE;
+  }
+  int lds_max = 65536;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess)
+    lds_max = 65536;
+  if (!shape_plan(p, (size_t)std::max(lds_max, 65536))) {
     delete p;
     return PPE_ERR_UNSUPPORTED;
   }
-  if (hipGetDevice(&p->device) != hipSuccess) {
+  if (p->lds_z > 65536 && allow_big_lds((int)p->lds_z) != hipSuccess) {
     delete p;
     return PPE_ERR_DEVICE;
   }

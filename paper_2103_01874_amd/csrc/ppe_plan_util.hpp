@@ -17,6 +17,9 @@ constexpr int kMaxN = 2048;  // longest FFT / y extent supported
 struct HostFft {
   int n = 0, e = 1, tc = 1, nst = 0;
   int radix[kMaxStages] = {0};
+  int ns[kMaxStages] = {0};
+  int tstep[kMaxStages] = {0};
+  float inv_ns[kMaxStages] = {0};
   double* tw = nullptr;  // device, 2n doubles
 };
 
@@ -47,7 +50,14 @@ inline bool fft_factor(int n, HostFft& f) {
   f.e = e;
   f.tc = n / e;
   f.nst = (int)r.size();
-  for (int s = 0; s < f.nst; ++s) f.radix[s] = r[s];
+  int ns = 1;
+  for (int s = 0; s < f.nst; ++s) {
+    f.radix[s] = r[s];
+    f.ns[s] = ns;
+    f.tstep[s] = n / (ns * r[s]);
+    f.inv_ns[s] = 1.0f / (float)ns;
+    ns *= r[s];
+  }
   return true;
 }
 

@@ -77,7 +77,9 @@ def test_workspace_accounts_for_precision_and_batch(lib):
     a = ws(nx=64, ny=32, nz=64)
     b = ws(nx=64, ny=32, nz=64, batch=4)
     m = ws(nx=64, ny=32, nz=64, precision=binding.PPE_PREC_MIXED)
-    spec64 = 64 * 32 * 33 * 16
+    # half spectrum in 128-byte kx tiles: 33 columns -> 5 tiles of 8 (FP64) or 3 tiles of 16 (FP32)
+    spec64 = 64 * 32 * 40 * 16
+    spec32 = 64 * 32 * 48 * 8
     assert b > 3 * a
-    # mixed: FP32 spectrum (half) plus an FP64 copy of b
-    assert m - a == -spec64 // 2 + 64 * 32 * 64 * 8
+    # mixed: FP32 spectrum plus the FP64 refinement residual buffer
+    assert m - a == spec32 - spec64 + 64 * 32 * 64 * 8
