@@ -195,7 +195,8 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   // columns + twiddle table (the plane-sum reduction reuses the column area)
   p->lds_z = std::max((size_t)d.nz * p->tx * 16, (size_t)p->tx * tcz * 8) + (size_t)d.nz * 16;
   // tri: P chunks of 2..16 rows, TXS systems per block
-  int P = (int)std::lround(d.ny / 8.0);
+  const int chunk = tune_env("PPE_TUNE_CHUNK") > 0 ? tune_env("PPE_TUNE_CHUNK") : 8;
+  int P = (int)std::lround(d.ny / (double)chunk);
   P = std::max(P, (d.ny + kMaxChunk - 1) / kMaxChunk);
   P = std::min(P, d.ny / 2);
   P = std::max(P, 1);
@@ -412,9 +413,10 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   PPE_TIMED(p, "k_rhs",
             PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads, march_lds(p->mrhs, 2),
                                                         p->stream>>>(tab, g, p->mrhs.m, W))));
-  finish(p, tab, inst0, nb, p->mrhs.grid, FIN_RHS, 0, tol);
+  // the right-hand-side sums are reduced by block 0 of the first row FFT
   PPE_TIMED(p, "k_r2c",
-            PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->b64, p->rp, 0))));
+            PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
+                                   tab, g, fx, W, p->b64, p->rp, 0, FinishArgs{p->mrhs.grid, tol}))));
   ppe_status_t st = launch_chain<TS>(p, W, nb, 0);
   if (st != PPE_OK) return st;
   PPE_TIMED(p, "k_c2r",
@@ -427,7 +429,8 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
                                                                                                     p->r64))));
       finish(p, tab, inst0, nb, p->mres.grid, FIN_RESID, 1);
       PPE_TIMED(p, "k_r2c",
-                PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(g, fx, W, p->r64, p->rp, 1))));
+                PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
+                                       tab, g, fx, W, p->r64, p->rp, 1, FinishArgs{0, 0.0}))));
       st = launch_chain<TS>(p, W, nb, 1);
       if (st != PPE_OK) return st;
       PPE_TIMED(p, "k_c2r",
