@@ -30,6 +30,16 @@ FFT solver handles periodic or homogeneous-Neumann boundaries):
   D  = cell divergence of face fluxes, G = face gradient of a cell field
   (zero on wall faces), L = D o G (7-point Laplacian, zero wall flux).
 
+Two y-boundary treatments (Grid.ybc):
+  ybc = 0  walls at both ends: zero pressure flux, v on both walls given.
+  ybc = 1  symmetry plane at the bottom (zero flux, v given) and an outflow
+           top boundary where p = 0 on the face (the paper's planar jets,
+           Sec. 6: symmetric jets with outflow at the top).  The top-face
+           gradient uses the antisymmetric ghost value, G p = -2 p_{ny-1}/dy,
+           the top-face density is that of the last cell, and the top v face is
+           corrected like any interior face.  L is then nonsingular: no
+           compatibility projection and no gauge.
+
 Readings of points the paper leaves open (each is listed in the design notes):
   * face density rho_f = arithmetic mean of the two adjacent cells, used in both
     the right-hand side and the projection (the same rho_f in both makes the
@@ -71,11 +81,14 @@ __all__ = [
 
 
 class Grid:
-    """Uniform staggered grid of nx*ny*nz cells, lengths lx, ly, lz (walls at both y ends)."""
+    """Uniform staggered grid of nx*ny*nz cells, lengths lx, ly, lz; ybc picks the y boundaries."""
 
-    def __init__(self, nx, ny, nz, lx=2 * np.pi, ly=2.0, lz=2 * np.pi):
+    def __init__(self, nx, ny, nz, lx=2 * np.pi, ly=2.0, lz=2 * np.pi, ybc=0):
         if min(nx, ny, nz) < 1:
             raise ValueError("grid sizes must be positive")
+        if ybc not in (0, 1):
+            raise ValueError("ybc is 0 (walls) or 1 (symmetry bottom, outflow top)")
+        self.ybc = int(ybc)
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.lx, self.ly, self.lz = float(lx), float(ly), float(lz)
         self.dx = self.lx / self.nx
@@ -140,13 +153,16 @@ def divergence(g: Grid, u, v, w):
 
 
 def gradient(g: Grid, p):
-    """Face gradient G of a cell field; zero on the wall faces of y."""
+    """Face gradient G of a cell field; zero on wall faces of y, and
+    -2 p_{ny-1}/dy on an outflow top face (p = 0 there)."""
     p = np.asarray(p, dtype=np.float64)
     gx = (p - np.roll(p, 1, axis=2)) / g.dx
     gz = (p - np.roll(p, 1, axis=0)) / g.dz
     nz, ny, nx = p.shape
     gy = np.zeros((nz, ny + 1, nx))
     gy[:, 1:ny, :] = (p[:, 1:, :] - p[:, :-1, :]) / g.dy
+    if g.ybc == 1:
+        gy[:, ny, :] = -2.0 * p[:, ny - 1, :] / g.dy
     return gx, gy, gz
 
 
@@ -159,7 +175,9 @@ def eigenvalues(g: Grid):
     """Closed-form eigenvalues of L on its eigenvectors (modified wavenumbers).
 
     lam_x(a) = -(4/dx^2) sin^2(pi a / nx)       periodic, a = 0..nx//2
-    lam_y(m) = -(4/dy^2) sin^2(pi m / (2 ny))   Neumann, cos(pi m (j+1/2)/ny)
+    lam_y(m) = -(4/dy^2) sin^2(pi m / (2 ny))   ybc 0: Neumann both ends, cos(pi m (j+1/2)/ny)
+    lam_y(m) = -(4/dy^2) sin^2(pi (2m+1)/(4 ny)) ybc 1: Neumann bottom, p = 0 on the top face,
+                                                  cos(pi (m+1/2)(j+1/2)/ny)
     lam_z(c) = -(4/dz^2) sin^2(pi c / nz)       periodic, c = 0..nz-1
     Returned broadcastable as [nz][ny][nx//2+1].
     """
@@ -167,7 +185,10 @@ def eigenvalues(g: Grid):
     m = np.arange(g.ny)
     c = np.arange(g.nz)
     lx = -(4.0 / g.dx**2) * np.sin(np.pi * a / g.nx) ** 2
-    ly = -(4.0 / g.dy**2) * np.sin(np.pi * m / (2.0 * g.ny)) ** 2
+    if g.ybc == 0:
+        ly = -(4.0 / g.dy**2) * np.sin(np.pi * m / (2.0 * g.ny)) ** 2
+    else:
+        ly = -(4.0 / g.dy**2) * np.sin(np.pi * (2 * m + 1) / (4.0 * g.ny)) ** 2
     lz = -(4.0 / g.dz**2) * np.sin(np.pi * c / g.nz) ** 2
     return lz[:, None, None] + ly[None, :, None] + lx[None, None, :]
 
@@ -192,20 +213,25 @@ def assemble_rhs(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, S):
 # ---------------------------------------------------------------------------
 
 def solve_spectral(g: Grid, b, workers=None):
-    """Full diagonalisation of L: rfft in x, fft in z, DCT-II in y.
+    """Full diagonalisation of L: rfft in x, fft in z, DCT-II (walls) or
+    DCT-IV (outflow top) in y.
 
-    The (0,0,0) coefficient carries mean(b); setting it to zero both removes
-    the incompatible part of b and imposes mean(p) = 0.
+    Walls: the (0,0,0) coefficient carries mean(b); setting it to zero both
+    removes the incompatible part of b and imposes mean(p) = 0.  Outflow: L is
+    nonsingular and every coefficient is divided.
     """
     b = np.asarray(b, dtype=np.float64)
+    ytype = 2 if g.ybc == 0 else 4
     bh = sfft.rfft(b, axis=2, workers=workers)
     bh = sfft.fft(bh, axis=0, workers=workers)
-    bh = sfft.dct(bh, type=2, axis=1, workers=workers)
+    bh = sfft.dct(bh, type=ytype, axis=1, workers=workers)
     lam = eigenvalues(g)
-    lam[0, 0, 0] = 1.0
+    if g.ybc == 0:
+        lam[0, 0, 0] = 1.0
     ph = bh / lam
-    ph[0, 0, 0] = 0.0
-    ph = sfft.idct(ph, type=2, axis=1, workers=workers)
+    if g.ybc == 0:
+        ph[0, 0, 0] = 0.0
+    ph = sfft.idct(ph, type=ytype, axis=1, workers=workers)
     ph = sfft.ifft(ph, axis=0, workers=workers)
     return sfft.irfft(ph, n=g.nx, axis=2, workers=workers)
 
@@ -226,10 +252,13 @@ def solve_dense(g: Grid, b):
     """Bordered dense solve [[L, 1], [1^T, 0]] [p; mu] = [b; 0] (tiny grids).
 
     Row sums of L vanish, so mu = mean(b) and L p = b - mean(b), sum(p) = 0.
+    With an outflow top L is nonsingular and is solved directly.
     """
     n = g.npts
     if n > 4096:
         raise ValueError("dense oracle is for tiny grids only")
+    if g.ybc == 1:
+        return np.linalg.solve(laplacian_matrix(g), np.asarray(b, dtype=np.float64).ravel()).reshape(g.shape)
     M = np.zeros((n + 1, n + 1))
     M[:n, :n] = laplacian_matrix(g)
     M[:n, n] = 1.0
@@ -247,7 +276,8 @@ def solve_dense(g: Grid, b):
 def correct(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, p):
     """u^{n+1} = u* - dt [ G p / rho0 + gamma_f G p_hat ],  gamma_f = 1/rho_f - 1/rho0.
 
-    Wall faces of v are not corrected: they keep v*.
+    Wall faces of v are not corrected: they keep v*.  An outflow top face is
+    corrected like an interior face.
     """
     ph = p_hat(pn, pnm1)
     rx, ry, rz = face_density(rho)
@@ -259,6 +289,8 @@ def correct(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, p):
     v[:, 1:-1, :] = vs[:, 1:-1, :] - dt * (
         py[:, 1:-1, :] / rho0 + (1.0 / ry[:, 1:-1, :] - 1.0 / rho0) * hy[:, 1:-1, :]
     )
+    if g.ybc == 1:
+        v[:, -1, :] = vs[:, -1, :] - dt * (py[:, -1, :] / rho0 + (1.0 / ry[:, -1, :] - 1.0 / rho0) * hy[:, -1, :])
     return u, v, w
 
 
@@ -270,7 +302,7 @@ def divergence_check(g: Grid, us, vs, ws, S, u, v, w):
     rel = ||D u - S_c||_2 / ||D u* - S_c||_2.
     """
     d0 = divergence(g, us, vs, ws) - S
-    compat = float(np.mean(d0))
+    compat = float(np.mean(d0)) if g.ybc == 0 else 0.0
     d0c = d0 - compat
     d = divergence(g, u, v, w) - S - compat
     l2 = float(np.sqrt(np.sum(d * d)))
@@ -285,7 +317,8 @@ def divergence_check(g: Grid, us, vs, ws, S, u, v, w):
 
 
 def solve(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, S, method="spectral", workers=None):
-    """Pressure of the split projection: zero-mean p with L p = b - mean(b)."""
+    """Pressure of the split projection: zero-mean p with L p = b - mean(b)
+    (walls), or p with L p = b (outflow top)."""
     r0 = rho0_of(rho, rho0)
     b = assemble_rhs(g, r0, dt, us, vs, ws, rho, pn, pnm1, S)
     if method == "spectral":
@@ -303,7 +336,7 @@ def ppe_step(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, S, method="spectral",
     u, v, w = correct(g, r0, dt, us, vs, ws, rho, pn, pnm1, p)
     chk = divergence_check(g, us, vs, ws, S, u, v, w)
     return {"p": p, "u": u, "v": v, "w": w, "rho0": r0, "b": b,
-            "compat_defect": float(np.mean(b)) * dt / r0, **chk}
+            "compat_defect": (float(np.mean(b)) * dt / r0) if g.ybc == 0 else 0.0, **chk}
 
 
 # ---------------------------------------------------------------------------
@@ -328,6 +361,8 @@ def solve_variable_coefficient_dense(g: Grid, dt, us, vs, ws, rho, S):
         A[:, col] = divergence(g, gx / rx, gy / ry, gz / rz).ravel()
         e[col] = 0.0
     d0 = divergence(g, us, vs, ws) - S
+    if g.ybc == 1:
+        return np.linalg.solve(A, (d0 / dt).ravel()).reshape(g.shape)
     rhs_c = (d0 - np.mean(d0)) / dt
     M = np.zeros((n + 1, n + 1))
     M[:n, :n] = A

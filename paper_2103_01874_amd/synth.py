@@ -11,6 +11,12 @@ Sec. 5.4, with C the exact liquid fraction of each cell in y.
 Layouts match the library: C order [nz][ny][nx]; u on west faces (nx per row),
 v on south faces (ny+1 per column, the two walls included), w on back faces.
 All arrays are float64 numpy arrays.
+
+``ybc`` names the y boundaries a request is posed with: 0 = walls at both ends
+(v* = 0 on both), 1 = symmetry plane at the bottom (v* = 0 there) and an
+outflow top whose v* is free.  The half-jet generator models the paper's
+planar jets, which are symmetric about the centre plane and leave the domain
+through an outflow boundary at the top (Sec. 6).
 """
 
 from __future__ import annotations
@@ -43,6 +49,7 @@ class Problem:
     pnm1: np.ndarray
     S: np.ndarray
     meta: Dict = dataclasses.field(default_factory=dict)
+    ybc: int = 0
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -98,12 +105,14 @@ def smooth_pressure(rng, nx, ny, nz, lx, ly, lz, amp=1e3, nterms=8, kmax=3):
     return amp * p
 
 
-def noise_velocity(rng, nx, ny, nz):
-    """u*, v*, w* ~ U(-1, 1) on every non-wall face; v* = 0 on both walls."""
+def noise_velocity(rng, nx, ny, nz, ybc=0):
+    """u*, v*, w* ~ U(-1, 1) on every non-wall face; v* = 0 on the walls
+    (both y ends for ybc 0, the bottom only for ybc 1)."""
     us = rng.uniform(-1.0, 1.0, size=(nz, ny, nx))
     vs = rng.uniform(-1.0, 1.0, size=(nz, ny + 1, nx))
     vs[:, 0, :] = 0.0
-    vs[:, ny, :] = 0.0
+    if ybc == 0:
+        vs[:, ny, :] = 0.0
     ws = rng.uniform(-1.0, 1.0, size=(nz, ny, nx))
     return us, vs, ws
 
@@ -181,16 +190,68 @@ def sheet_problem(nx, ny, nz, *, seed, rho_l=640.0, rho_g=100.0, h0=0.3, modes=N
     return Problem(nx, ny, nz, lx, ly, lz, rho_g, dt, us, vs, ws, rho, pn, pnm1, S, meta)
 
 
-def random_problem(nx, ny, nz, *, seed, lx=TWO_PI, ly=2.0, lz=TWO_PI, dt=1e-3) -> Problem:
+def random_problem(nx, ny, nz, *, seed, lx=TWO_PI, ly=2.0, lz=TWO_PI, dt=1e-3, ybc=0) -> Problem:
     """Unstructured test request: random density in [1, 10] and random fields."""
     rng = np.random.default_rng(seed)
     rho = rng.uniform(1.0, 10.0, size=(nz, ny, nx))
-    us, vs, ws = noise_velocity(rng, nx, ny, nz)
+    us, vs, ws = noise_velocity(rng, nx, ny, nz, ybc)
     S = rng.standard_normal((nz, ny, nx))
     pn = rng.standard_normal((nz, ny, nx))
     pnm1 = rng.standard_normal((nz, ny, nx))
     return Problem(nx, ny, nz, lx, ly, lz, float(rho.min()), dt, us, vs, ws, rho, pn, pnm1, S,
-                   dict(seed=seed, kind="random"))
+                   dict(seed=seed, kind="random"), ybc)
+
+
+def half_sheet_fraction(nx, ny, nz, lx, ly, lz, h0: float, modes):
+    """Exact y-overlap of each cell of [0, ly] with the liquid 0 <= y < h0 + eta(x, z)
+    (the upper half of a sheet symmetric about y = 0; eta as in liquid_fraction)."""
+    x = _centres(nx, lx)
+    z = _centres(nz, lz)
+    eta = np.zeros((nz, nx))
+    for a, kx, phx, kz, phz in modes:
+        eta += a * np.cos(kz * TWO_PI * z / lz + phz)[:, None] * np.sin(kx * TWO_PI * x / lx + phx)[None, :]
+    h = np.clip(h0 + eta, 0.0, ly)
+    dy = ly / ny
+    ylo = np.arange(ny) * dy
+    hi = np.minimum(ylo[None, :, None] + dy, h[:, None, :])
+    return np.clip(hi - ylo[None, :, None], 0.0, None) / dy
+
+
+def outflow_pressure(rng, nx, ny, nz, lx, ly, lz, amp=1e3, nterms=8, kmax=3):
+    """Sum of separable modes that are even about y = 0 and vanish at y = ly."""
+    x = _centres(nx, lx)
+    y = _centres(ny, ly)
+    z = _centres(nz, lz)
+    p = np.zeros((nz, ny, nx))
+    for _ in range(nterms):
+        a, m, e = rng.integers(0, kmax + 1, size=3)
+        phx, phz = rng.uniform(0, TWO_PI, size=2)
+        c = rng.standard_normal()
+        fx = np.cos(a * TWO_PI * x / lx + phx)
+        fy = np.cos(np.pi * (m + 0.5) * y / ly)
+        fz = np.cos(e * TWO_PI * z / lz + phz)
+        p += c * fz[:, None, None] * fy[None, :, None] * fx[None, None, :]
+    return amp * p
+
+
+def jet_problem(nx, ny, nz, *, seed, rho_l=640.0, rho_g=100.0, h0=0.3, modes=None, nmodes=3,
+                dt=1e-3, lx=TWO_PI, ly=1.0, lz=TWO_PI, s_amp=1e-3, p_amp=1e3,
+                outflow_v=0.05) -> Problem:
+    """Half of a planar jet: liquid below h(x, z) over a symmetry plane at y = 0,
+    gas above, outflow at y = ly (ybc 1).  u*, w* ~ U(-1, 1); v* ~ U(-1, 1) inside,
+    0 on the symmetry plane and outflow_v + 0.1 U(-1, 1) on the top face."""
+    rng = np.random.default_rng(seed)
+    if modes is None:
+        modes = random_modes(rng, nmodes)
+    C = half_sheet_fraction(nx, ny, nz, lx, ly, lz, h0, modes)
+    rho = rho_g + (rho_l - rho_g) * C
+    us, vs, ws = noise_velocity(rng, nx, ny, nz, 1)
+    vs[:, ny, :] = outflow_v + 0.1 * rng.uniform(-1.0, 1.0, size=(nz, nx))
+    S = interface_source(rng, C, s_amp)
+    pn = outflow_pressure(np.random.default_rng(seed + 7919), nx, ny, nz, lx, ly, lz, amp=p_amp)
+    pnm1 = 0.9 * outflow_pressure(np.random.default_rng(seed + 104729), nx, ny, nz, lx, ly, lz, amp=p_amp)
+    meta = dict(seed=seed, rho_l=rho_l, rho_g=rho_g, h0=h0, modes=modes, kind="half_jet")
+    return Problem(nx, ny, nz, lx, ly, lz, rho_g, dt, us, vs, ws, rho, pn, pnm1, S, meta, 1)
 
 
 # ---------------------------------------------------------------------------
@@ -213,6 +274,16 @@ def sheet_512(seed=3000, velocity="noise") -> Problem:
     """512x256x512 sheet, rho 640/60, 5 random interface modes."""
     return sheet_problem(512, 256, 512, seed=seed, rho_l=640.0, rho_g=60.0, h0=0.3,
                          nmodes=5, velocity=velocity)
+
+
+def jet_32(seed=5000) -> Problem:
+    """32^3 half jet over a symmetry plane with an outflow top, rho 640/100."""
+    return jet_problem(32, 32, 32, seed=seed, modes=[(0.02, 1, 0.0, 1, 0.0)])
+
+
+def jet_256(seed=6000) -> Problem:
+    """256x128x256 half jet over a symmetry plane with an outflow top, rho 640/100."""
+    return jet_problem(256, 128, 256, seed=seed, nmodes=3)
 
 
 BATCH_SHAPES = [(64, 64, 64), (96, 64, 96), (128, 64, 128), (192, 96, 192)]
