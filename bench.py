@@ -39,6 +39,8 @@ WORKLOADS = {
                                 "FP32 spectra + FP64 refinement to 1e-12, 512x256x512 sheet rho 640/60"),
     "sheet_512x256x512_fp64": ("sheet_512", 0, 0, "FP64 direct solve, 512x256x512 sheet rho 640/60"),
     "sheet_32_fp64": ("sheet_32", 0, 0, "FP64 direct solve, 32^3 sheet rho 640/100"),
+    "jet_256x128x256_fp64": ("jet_256", 0, 0, "FP64 direct solve, 256x128x256 half jet over a symmetry plane "
+                                               "with an outflow (p = 0) top, rho 640/100"),
     "batch_48_mixed": ("batch_48", 1, 1, "48 independent sheets of uneven sizes {64^3, 96x64x96, 128x64x128, "
                                           "192x96x192}, rho ratio U(3,12), FP32 spectra + FP64 refinement, "
                                           "same-shape instances batched per launch"),
@@ -86,7 +88,7 @@ def cpu_baseline(pr, budget_s: float = 12.0):
     import oracle as O
 
     workers = max(1, min(16, os.cpu_count() or 1))
-    g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz)
+    g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=pr.ybc)
     steps = 0
     t0 = time.perf_counter()
     while True:
@@ -290,7 +292,7 @@ def main():
     stream = torch.cuda.Stream(dev)
     with torch.cuda.stream(stream):
         plan = binding.Plan(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, precision=precision, tol=1e-12,
-                            max_refine=max_refine, stream=stream)
+                            max_refine=max_refine, stream=stream, ybc=pr.ybc)
         fields = binding.to_device(pr, dev)
         outs = {"p": torch.empty_like(fields["rho"]), "u": torch.empty_like(fields["us"]),
                 "v": torch.empty_like(fields["vs"]), "w": torch.empty_like(fields["ws"])}
@@ -375,6 +377,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "grid": [pr.nx, pr.ny, pr.nz],
                    "points": npts, "precision": "fp64" if precision == 0 else "mixed",
+                   "y_boundaries": "walls" if pr.ybc == 0 else "symmetry bottom, outflow top",
                    "max_refine": max_refine, "parallelism": "single GPU"},
         "result": {"eps_div": rec["res_rel"], "iters": rec["iters"], "status": rec["status"]},
         "roofline": roofline,

@@ -16,18 +16,25 @@
  *
  * Grid and layouts (all fields are C-order float64, x fastest):
  *   nx*ny*nz cells of size dx = lx/nx, dy = ly/ny, dz = lz/nz; x and z are
- *   periodic, y is bounded by two walls.
+ *   periodic; the y ends are chosen by ppe_desc_t.ybc (ppe_ybc_t).
  *   cell fields rho, p^n, p^{n-1}, S, p : [nz][ny][nx]
  *   u (west face of cell i)             : [nz][ny][nx]
- *   v (south face of cell j)            : [nz][ny+1][nx]; rows 0 and ny are
- *                                         the walls (read as given, never
- *                                         corrected, zero pressure flux)
+ *   v (south face of cell j)            : [nz][ny+1][nx]; row 0 is a wall or
+ *                                         symmetry plane (read as given, never
+ *                                         corrected, zero pressure flux); row
+ *                                         ny is a wall likewise (PPE_YBC_WALLS)
+ *                                         or an outflow face (PPE_YBC_OUTFLOW)
  *   w (back face of cell k)             : [nz][ny][nx]
  *   D = cell divergence, G = face gradient (zero on walls), L = D o G.
  *   Face density rho_f = (rho_a + rho_b)/2, the same in the right-hand side
- *   and in the projection, so div u^{n+1} = S_c to rounding, with
- *   S_c = S + mean(D u* - S).  The pressure is fixed by mean(p) = 0, and
- *   mean(b) is removed from the right-hand side (compatibility).
+ *   and in the projection, so div u^{n+1} = S_c to rounding.
+ *   PPE_YBC_WALLS: L is singular; S_c = S + mean(D u* - S), mean(b) is
+ *   removed from the right-hand side (compatibility) and the pressure is
+ *   fixed by mean(p) = 0.
+ *   PPE_YBC_OUTFLOW (the planar jets of Sec. 6, computed over their symmetry
+ *   plane): p = 0 on the top face, imposed by the ghost value -p_{ny-1}; the
+ *   top face's density is rho_{ny-1}; the top v face is corrected like an
+ *   interior face.  L is regular: S_c = S, nothing is removed, no gauge.
  *
  * Ownership: every field pointer is a DEVICE pointer owned by the caller;
  * the plan owns its workspace, twiddle and eigenvalue tables (allocated in
@@ -68,6 +75,13 @@ typedef enum {
   PPE_ERR_UNSUPPORTED = -6   /* FFT length not of the form 2^a 3^b, or too long */
 } ppe_status_t;
 
+/* Boundaries at the two ends of y (x and z are always periodic). */
+typedef enum {
+  PPE_YBC_WALLS = 0,   /* zero pressure flux through both end faces */
+  PPE_YBC_OUTFLOW = 1  /* zero flux through the bottom face (wall or symmetry
+                          plane), p = 0 on the top face (outflow) */
+} ppe_ybc_t;
+
 /* Precision of the spectral passes (FFTs and tridiagonal sweeps). */
 typedef enum {
   PPE_PREC_FP64 = 0,   /* FP64 storage and arithmetic: the direct solve */
@@ -79,6 +93,7 @@ typedef struct {
   int32_t nx, ny, nz;      /* cells; nx, nz in 1..2048 of the form 2^a 3^b; 2 <= ny <= 2048 */
   double lx, ly, lz;       /* domain lengths (> 0) */
   int32_t precision;       /* ppe_precision_t */
+  int32_t ybc;             /* ppe_ybc_t */
   double tol;              /* PPE_PREC_MIXED: stop when the relative residual
                               ||b - mean b - L p||_2 / ||(rho0/dt)(D u* - S_c)||_2
                               <= tol (the projected field's relative
@@ -93,13 +108,15 @@ typedef struct {
   int32_t status;          /* ppe_status_t (PPE_OK, NOT_CONVERGED, NONFINITE) */
   int32_t iters;           /* refinement sweeps run (0 for PPE_PREC_FP64) */
   double rho0_used;        /* rho0 actually used */
-  double compat_defect;    /* mean(D u* - S): the incompatible part removed */
+  double compat_defect;    /* mean(D u* - S): the incompatible part removed
+                              (0 for PPE_YBC_OUTFLOW) */
   double res_rel;          /* ppe_solve: last refinement residual (relative);
                               ppe_correct: div_l2 / div0_l2 */
   double div_l2;           /* ppe_correct: ||D u^{n+1} - S_c||_2 */
   double div_max;          /* ppe_correct: max |D u^{n+1} - S_c| */
   double div0_l2;          /* ||D u* - S_c||_2 */
-  double p_mean;           /* ppe_solve: mean of the returned p (gauge check) */
+  double p_mean;           /* ppe_correct: mean of p (0 up to rounding for
+                              PPE_YBC_WALLS: the gauge) */
 } ppe_info_t;
 
 /* Maximum number of instances per call; larger batches need several calls. */
@@ -124,7 +141,8 @@ ppe_status_t ppe_plan_set_stream(ppe_plan_t plan, void* stream);
  *   rho0[b] : host array; > 0 is used as given, <= 0 requests min(rho) (device)
  *   dt[b]   : host array, > 0
  *   us, vs, ws, rho, pn, pnm1, S : host arrays of `batch` device pointers (inputs)
- *   p       : host array of `batch` device pointers (output, zero-mean)
+ *   p       : host array of `batch` device pointers (output; zero-mean for
+ *             PPE_YBC_WALLS)
  *   info    : device array of `batch` records (output)
  * For PPE_PREC_MIXED the first solve uses FP32 spectra and is refined with
  * FP64 residuals until `tol` or `max_refine`. */
@@ -138,7 +156,7 @@ ppe_status_t ppe_solve(ppe_plan_t plan, const double* rho0, const double* dt,
  * the same inputs) and writes div_l2, div_max, div0_l2, res_rel and status
  * (PPE_ERR_NOT_CONVERGED when res_rel > desc.tol > 0).
  *   u, v, w : host arrays of `batch` device pointers (outputs; the wall rows
- *             of v are copied from v*). */
+ *             of v are copied from v*, an outflow row is corrected). */
 ppe_status_t ppe_correct(ppe_plan_t plan, const double* dt,
                          const double* const* us, const double* const* vs, const double* const* ws,
                          const double* const* rho, const double* const* pn, const double* const* pnm1,
@@ -147,7 +165,9 @@ ppe_status_t ppe_correct(ppe_plan_t plan, const double* dt,
 
 /* Continuity diagnostic of any staggered field (the constraint behind
  * Eq. 25): out[3*b + 0] = ||d - mean d||_2, out[3*b + 1] = max |d - mean d|,
- * out[3*b + 2] = mean d, with d = D u - S.  `out` is a device array. */
+ * out[3*b + 2] = mean d, with d = D u - S.  `out` is a device array.  (The
+ * mean is removed for either ybc; with an outflow top the projected field's
+ * mean d is itself zero to rounding.) */
 ppe_status_t ppe_residual(ppe_plan_t plan, const double* const* u, const double* const* v,
                           const double* const* w, const double* const* S, double* out);
 

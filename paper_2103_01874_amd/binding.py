@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libppe.so")
 
 PPE_PREC_FP64 = 0
 PPE_PREC_MIXED = 1
+PPE_YBC_WALLS = 0
+PPE_YBC_OUTFLOW = 1
 MAX_BATCH = 64
 
 STATUS = {0: "ok", -1: "bad argument", -2: "out of memory", -3: "device error", -4: "not converged",
@@ -32,8 +34,11 @@ class PPEError(RuntimeError):
 class Desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("batch", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("ybc", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_refine", ctypes.c_int32), ("batch", ctypes.c_int32)]
+
+
+assert ctypes.sizeof(Desc) == 64
 
 
 INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("rho0_used", "<f8"), ("compat_defect", "<f8"),
@@ -94,9 +99,9 @@ def load(path: str = LIB_PATH):
 
 
 def make_desc(nx, ny, nz, lx=2 * np.pi, ly=2.0, lz=2 * np.pi, precision=PPE_PREC_FP64, tol=1e-12,
-              max_refine=1, batch=1) -> Desc:
-    return Desc(int(nx), int(ny), int(nz), float(lx), float(ly), float(lz), int(precision), float(tol),
-                int(max_refine), int(batch))
+              max_refine=1, batch=1, ybc=PPE_YBC_WALLS) -> Desc:
+    return Desc(int(nx), int(ny), int(nz), float(lx), float(ly), float(lz), int(precision), int(ybc),
+                float(tol), int(max_refine), int(batch))
 
 
 def workspace_bytes(desc: Desc) -> int:
@@ -133,12 +138,12 @@ class Plan:
     """A plan for `batch` same-shape instances, bound to a torch CUDA stream."""
 
     def __init__(self, nx, ny, nz, lx=2 * np.pi, ly=2.0, lz=2 * np.pi, precision=PPE_PREC_FP64, tol=1e-12,
-                 max_refine=1, batch=1, stream=None, device=None):
+                 max_refine=1, batch=1, stream=None, device=None, ybc=PPE_YBC_WALLS):
         import torch
 
         self._torch = torch
         self.lib = load()
-        self.desc = make_desc(nx, ny, nz, lx, ly, lz, precision, tol, max_refine, batch)
+        self.desc = make_desc(nx, ny, nz, lx, ly, lz, precision, tol, max_refine, batch, ybc)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._h = ctypes.c_void_p()

@@ -52,7 +52,7 @@ void run_fft(const HostFft& h, const std::vector<double>& tw, cplx<double>* buf)
 }
 
 template <int MC>
-void run_tri(int ny, int P, double s, int zero, const double* rhs, double* x) {
+void run_tri(int ny, int P, double s, int zero, int outflow, const double* rhs, double* x) {
   std::vector<RedRow<double>> red(2 * (size_t)P);
   std::vector<cplx<double>> r((size_t)P * MC);
   std::vector<double> phi((size_t)P * MC), psi((size_t)P * MC);
@@ -69,7 +69,7 @@ void run_tri(int ny, int P, double s, int zero, const double* rhs, double* x) {
     const cplx<double> rf = rr[0], rl = rr[m - 1];
     chunk_eliminate<MC>(rr, m, s, &phi[(size_t)p * MC], &psi[(size_t)p * MC]);
     RedRow<double> f, l;
-    chunk_reduced_rows<MC>(rr, rf, rl, m, s, p == 0, p == P - 1, &phi[(size_t)p * MC], &psi[(size_t)p * MC], f, l);
+    chunk_reduced_rows<MC>(rr, rf, rl, m, s, p == 0, p == P - 1, outflow != 0, &phi[(size_t)p * MC], &psi[(size_t)p * MC], f, l);
     if (zero && p == 0) {
       f.a = 0.0;
       f.b = 1.0;
@@ -168,14 +168,16 @@ int hc_fft(int n, int dir, const double* in, double* out) {
 }
 
 // One y system: x_{j-1} + beta_j x_j + x_{j+1} = rhs_j (scaled form, complex
-// interleaved), P chunks; zero != 0 applies the pin and the mean removal of
-// the (0,0) system.
-int hc_tri(int ny, int P, double s, int zero, const double* rhs, double* x) {
+// interleaved), P chunks.  flags bit 0: apply the pin and the mean removal of
+// the singular (0,0) system; bit 1: outflow top row (beta_{ny-1} = -3 - s).
+int hc_tri(int ny, int P, double s, int flags, const double* rhs, double* x) {
   if (P < 1 || ny < 2 * P) return -1;
+  const int zero = flags & 1, outflow = (flags >> 1) & 1;
+  if (zero && outflow) return -1;  // the outflow system is never singular
   const int mmax = (ny + P - 1) / P;
-  if (mmax <= 4) run_tri<4>(ny, P, s, zero, rhs, x);
-  else if (mmax <= 8) run_tri<8>(ny, P, s, zero, rhs, x);
-  else if (mmax <= 16) run_tri<16>(ny, P, s, zero, rhs, x);
+  if (mmax <= 4) run_tri<4>(ny, P, s, zero, outflow, rhs, x);
+  else if (mmax <= 8) run_tri<8>(ny, P, s, zero, outflow, rhs, x);
+  else if (mmax <= 16) run_tri<16>(ny, P, s, zero, outflow, rhs, x);
   else return -1;
   return 0;
 }

@@ -304,7 +304,9 @@ __device__ __forceinline__ void fft_lds(BufT* buf, int es, int t, bool active, c
 //
 // Scaled system for one wavenumber pair (multiplied by dy^2):
 //   x_{j-1} + beta_j x_j + x_{j+1} = r_j,  beta_j = -2 - s (interior),
-//   beta_0 = beta_{ny-1} = -1 - s (zero-flux walls), s = -(lam_x + lam_z) dy^2 >= 0.
+//   beta_0 = -1 - s (zero-flux bottom face), beta_{ny-1} = -1 - s (zero-flux
+//   top face) or -3 - s (outflow top face, p = 0 there: ghost x_ny = -x_{ny-1}),
+//   s = -(lam_x + lam_z) dy^2 >= 0.
 // A chunk [j0, j1] (m = j1 - j0 + 1 rows) eliminates its interior rows as a
 // Dirichlet problem with end values x_{j0}, x_{j1}:
 //   x_i = y_i + phi_i x_{j0} + psi_i x_{j1},  i = 1..m-2 (local index)
@@ -368,10 +370,10 @@ struct RedRow {
 
 template <int MC, typename T>
 PPE_HD void chunk_reduced_rows(const cplx<T>* r, const cplx<T>& r_first, const cplx<T>& r_last, int m, T s,
-                               bool global_first, bool global_last, const T* phi, const T* psi, RedRow<T>& f,
-                               RedRow<T>& l) {
+                               bool global_first, bool global_last, bool top_outflow, const T* phi,
+                               const T* psi, RedRow<T>& f, RedRow<T>& l) {
   const T beta_first = global_first ? (-T(1) - s) : (-T(2) - s);
-  const T beta_last = global_last ? (-T(1) - s) : (-T(2) - s);
+  const T beta_last = global_last ? ((top_outflow ? -T(3) : -T(1)) - s) : (-T(2) - s);
   const int ni = m - 2;
   // x_{j0+1} = y_1 + phi_1 first + psi_1 last   (x_{j1} itself when m == 2)
   T phi1 = T(0), psi1 = T(1), phiL = T(1), psiL = T(0);

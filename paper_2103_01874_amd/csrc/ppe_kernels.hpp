@@ -7,8 +7,9 @@
 //                with the real FFT along x (two rows packed per complex FFT)
 //   k_fft_z      complex FFT along z, in place on the half spectrum
 //   k_tri        one tridiagonal system in y per (kx, kz), partition method;
-//                the (0,0) system (singular) is compatible-projected, pinned
-//                and gauge-fixed in FP64 from FP64 plane sums
+//                the (0,0) system is solved in FP64 from FP64 plane sums
+//                (with zero-flux ends it is singular: compatible-projected,
+//                pinned and gauge-fixed)
 //   k_fft_z      inverse
 //   k_c2r        inverse real FFT along x -> p (or p update when refining)
 //   k_residual   FP64 r = b - L p fused with the real FFT of r (refinement)
@@ -27,10 +28,10 @@ constexpr int kRedBlocks = 2048;   // grid cap of the grid-stride reduction kern
 enum ScalarSlot {
   SC_RHO0 = 0,    // rho0 used
   SC_DT,          // dt
-  SC_COMPAT,      // mean(D u* - S)
+  SC_COMPAT,      // mean(D u* - S) (0 with an outflow top)
   SC_REF2,        // ||(rho0/dt)(D u* - S_c)||^2  (refinement stop scale)
-  SC_BMEAN,       // mean(b)
-  SC_PMEAN,       // mean of the current p (refinement)
+  SC_BMEAN,       // mean(b) (0 with an outflow top: nothing is removed)
+  SC_PMEAN,       // mean of the current p (refinement gauge; 0 with an outflow top)
   SC_CONV,        // 1 once the refinement met tol
   SC_RES,         // last relative residual
   SC_ITERS,       // refinement sweeps run
@@ -61,6 +62,7 @@ struct PtrTable {
 
 struct Geom {
   int nx, ny, nz, hx;
+  int ybc;              // 0: zero-flux faces at both y ends; 1: outflow top (p = 0 on the face)
   int tws;              // log2 of the spectrum tile width (128-byte tiles of kx)
   long long npts;       // nx*ny*nz
   long long spec_elems; // ntiles * nz * ny * tile width (>= hx * ny * nz)

@@ -110,6 +110,7 @@ bool desc_ok(const ppe_desc_t* d) {
   if (d->nx > kMaxN || d->nz > kMaxN || d->ny > kMaxN) return false;
   if (!(d->lx > 0) || !(d->ly > 0) || !(d->lz > 0)) return false;
   if (d->precision != PPE_PREC_FP64 && d->precision != PPE_PREC_MIXED) return false;
+  if (d->ybc != PPE_YBC_WALLS && d->ybc != PPE_YBC_OUTFLOW) return false;
   if (d->batch < 1 || d->batch > PPE_MAX_BATCH) return false;
   if (d->max_refine < 0 || d->max_refine > 64) return false;
   if (!(d->tol >= 0)) return false;
@@ -168,6 +169,7 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   g.ny = d.ny;
   g.nz = d.nz;
   g.hx = d.nx / 2 + 1;
+  g.ybc = d.ybc;
   g.tws = d.precision == PPE_PREC_FP64 ? 3 : 4;  // 128-byte kx tiles
   g.npts = (long long)d.nx * d.ny * d.nz;
   const long long ntile = (g.hx + (1 << g.tws) - 1) >> g.tws;

@@ -42,6 +42,7 @@ class Request:
     dt: float
     arrival: float                 # seconds on the server clock
     lengths: Tuple[float, float, float] = (2 * math.pi, 2.0, 2 * math.pi)
+    ybc: int = 0                   # y boundaries (0 walls, 1 symmetry bottom + outflow top)
     # filled by the server
     admitted: Optional[float] = None
     launched: Optional[float] = None
@@ -54,6 +55,11 @@ class Request:
     @property
     def npts(self) -> int:
         return self.shape[0] * self.shape[1] * self.shape[2]
+
+    @property
+    def plan_key(self):
+        """Requests with equal keys can share a plan and a batched launch."""
+        return (self.shape, tuple(self.lengths), self.ybc)
 
     @property
     def latency(self) -> Optional[float]:
@@ -78,7 +84,7 @@ class Backend:
     def plan_bytes(self, shape: Shape, batch: int) -> int:
         raise NotImplementedError
 
-    def make_plan(self, slot: int, shape: Shape, batch: int, lengths) -> object:
+    def make_plan(self, slot: int, shape: Shape, batch: int, lengths, ybc: int = 0) -> object:
         raise NotImplementedError
 
     def free_plan(self, plan: object) -> None:
@@ -146,15 +152,15 @@ class Server:
         self.ready.append(req)
         return True
 
-    def _plan(self, slot: int, shape: Shape, batch: int, lengths):
-        key = (slot, shape, batch)
+    def _plan(self, slot: int, req: Request, batch: int):
+        key = (slot, req.plan_key, batch)
         if key in self.plans:
             self.plans.move_to_end(key)
             return key, self.plans[key][0]
-        nbytes = self.b.plan_bytes(shape, batch)
+        nbytes = self.b.plan_bytes(req.shape, batch)
         if not self._evict(nbytes):
             return None, None
-        plan = self.b.make_plan(slot, shape, batch, lengths)
+        plan = self.b.make_plan(slot, req.shape, batch, req.lengths, req.ybc)
         self.plans[key] = (plan, nbytes)
         self.used += nbytes
         return key, plan
@@ -167,15 +173,15 @@ class Server:
             if slot in self.inflight:
                 continue
             head = self.ready[0]
-            same = [r for r in self.ready if r.shape == head.shape][: self.max_group]
+            same = [r for r in self.ready if r.plan_key == head.plan_key][: self.max_group]
             # batch sizes are powers of two so that few plans serve every group
             g = 1 << (len(same).bit_length() - 1)
             group = same[:g]
-            key, plan = self._plan(slot, head.shape, g, head.lengths)
+            key, plan = self._plan(slot, head, g)
             if plan is None and g > 1:
                 g = 1
                 group = same[:1]
-                key, plan = self._plan(slot, head.shape, 1, head.lengths)
+                key, plan = self._plan(slot, head, 1)
             if plan is None:
                 if not self.inflight:
                     # nothing will free memory: the head request cannot be served
@@ -302,10 +308,10 @@ class GpuBackend(Backend):
             self._ws[key] = self.binding.workspace_bytes(d)
         return self._ws[key]
 
-    def make_plan(self, slot, shape, batch, lengths):
+    def make_plan(self, slot, shape, batch, lengths, ybc=0):
         nx, ny, nz = shape
         return self.binding.Plan(nx, ny, nz, *lengths, precision=self.precision, tol=self.tol,
-                                 max_refine=self.max_refine, batch=batch, stream=self.streams[slot])
+                                 max_refine=self.max_refine, batch=batch, stream=self.streams[slot], ybc=ybc)
 
     def free_plan(self, plan):
         plan.close()
@@ -341,10 +347,11 @@ class GpuBackend(Backend):
 
 
 def group_by_shape(reqs: Sequence[Request], max_batch: int) -> List[List[Request]]:
-    """Same-shape requests in groups of at most max_batch, in first-seen order."""
-    by: "collections.OrderedDict[Shape, List[Request]]" = collections.OrderedDict()
+    """Requests of one plan key (shape, lengths, y boundaries) in groups of at
+    most max_batch, in first-seen order."""
+    by: "collections.OrderedDict[tuple, List[Request]]" = collections.OrderedDict()
     for r in reqs:
-        by.setdefault(r.shape, []).append(r)
+        by.setdefault(r.plan_key, []).append(r)
     out = []
     for lst in by.values():
         for i in range(0, len(lst), max_batch):
@@ -357,7 +364,7 @@ def solve_batch(backend: GpuBackend, reqs: Sequence[Request], max_batch: int = 6
     group, groups spread over the backend's streams.  Returns timing."""
     torch = backend.torch
     groups = group_by_shape(reqs, max_batch)
-    plans = [backend.make_plan(i % len(backend.streams), g[0].shape, len(g), g[0].lengths)
+    plans = [backend.make_plan(i % len(backend.streams), g[0].shape, len(g), g[0].lengths, g[0].ybc)
              for i, g in enumerate(groups)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -28,7 +28,7 @@ def gpu_step(problems, precision=binding.PPE_PREC_FP64, tol=1e-12, max_refine=2,
     torch = _torch()
     pr0 = problems[0]
     plan = binding.Plan(pr0.nx, pr0.ny, pr0.nz, pr0.lx, pr0.ly, pr0.lz, precision=precision, tol=tol,
-                        max_refine=max_refine, batch=len(problems))
+                        max_refine=max_refine, batch=len(problems), ybc=pr0.ybc)
     fields = [binding.to_device(pr) for pr in problems]
     r0 = [pr.rho0 for pr in problems] if rho0 is None else rho0
     outs, info = binding.step(plan, fields, r0, [pr.dt for pr in problems])
@@ -39,9 +39,9 @@ def gpu_step(problems, precision=binding.PPE_PREC_FP64, tol=1e-12, max_refine=2,
     return res, recs
 
 
-def oracle_step(pr, rho0=None):
-    g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz)
-    return O.ppe_step(g, pr.rho0 if rho0 is None else rho0, pr.dt, *pr.fields())
+def oracle_step(pr, rho0=None, method="spectral"):
+    g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=pr.ybc)
+    return O.ppe_step(g, pr.rho0 if rho0 is None else rho0, pr.dt, *pr.fields(), method=method)
 
 
 def errors(pr, got, ref):
@@ -60,10 +60,18 @@ def check(pr, got, rec, ref, tol=TOL):
     assert e["eps_du"] <= tol, e
     assert rec["res_rel"] <= tol, rec
     assert abs(rec["rho0_used"] - ref["rho0"]) <= 1e-15 * ref["rho0"]
-    assert abs(rec["p_mean"]) <= 1e-13 * np.abs(ref["p"]).max()
     # v on the walls is copied, never corrected
     assert np.array_equal(got["v"][:, 0, :], pr.vs[:, 0, :])
-    assert np.array_equal(got["v"][:, -1, :], pr.vs[:, -1, :])
+    if pr.ybc == 0:
+        assert abs(rec["p_mean"]) <= 1e-13 * np.abs(ref["p"]).max()
+        assert np.array_equal(got["v"][:, -1, :], pr.vs[:, -1, :])
+        scale = abs(ref["compat"]) + ref["div0_l2"] / np.sqrt(pr.npts)
+        assert abs(rec["compat_defect"] - ref["compat"]) <= 1e-13 * scale
+    else:
+        # outflow top: nothing removed, no gauge, top face corrected
+        assert rec["compat_defect"] == 0.0
+        assert abs(rec["p_mean"] - ref["p"].mean()) <= 1e-12 * np.abs(ref["p"]).max()
+        assert not np.array_equal(got["v"][:, -1, :], pr.vs[:, -1, :])
 
 
 TINY = [(6, 4, 6), (12, 5, 9), (8, 3, 4), (4, 2, 3), (9, 7, 12), (1, 4, 8), (8, 4, 1), (32, 16, 24),
@@ -80,9 +88,7 @@ def test_fp64_random_fields_tiny(shape):
 def test_fp64_dense_oracle_tiny():
     pr = synth.random_problem(6, 5, 6, seed=3)
     (got,), (rec,) = gpu_step([pr])
-    g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz)
-    ref = O.ppe_step(g, pr.rho0, pr.dt, *pr.fields(), method="dense")
-    check(pr, got, rec, ref)
+    check(pr, got, rec, oracle_step(pr, method="dense"))
 
 
 def test_fp64_sheet_32():
@@ -145,3 +151,54 @@ def test_residual_entry_point():
     assert abs(o0[0] - np.linalg.norm(d0 - d0.mean())) <= 1e-12 * np.linalg.norm(d0)
     assert o[0] <= 1e-12 * o0[0]
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Symmetry-plane bottom, outflow (p = 0) top: the planar jets' y boundaries
+# ---------------------------------------------------------------------------
+
+OUTFLOW_TINY = [(6, 4, 6), (12, 5, 9), (8, 3, 4), (4, 2, 3), (9, 7, 12), (1, 4, 8), (8, 4, 1), (32, 16, 24),
+                (48, 33, 18)]
+
+
+@pytest.mark.parametrize("shape", OUTFLOW_TINY)
+def test_outflow_fp64_random_fields_tiny(shape):
+    pr = synth.random_problem(*shape, seed=7 * sum(shape), ybc=1)
+    (got,), (rec,) = gpu_step([pr])
+    check(pr, got, rec, oracle_step(pr))
+
+
+def test_outflow_fp64_dense_oracle_tiny():
+    pr = synth.random_problem(6, 5, 6, seed=4, ybc=1)
+    (got,), (rec,) = gpu_step([pr])
+    check(pr, got, rec, oracle_step(pr, method="dense"))
+
+
+def test_outflow_fp64_jet_32():
+    pr = synth.jet_32()
+    (got,), (rec,) = gpu_step([pr])
+    check(pr, got, rec, oracle_step(pr))
+
+
+def test_outflow_fp64_jet_256x128x256_full_oracle():
+    pr = synth.jet_256()
+    (got,), (rec,) = gpu_step([pr])
+    check(pr, got, rec, oracle_step(pr))
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (96, 64, 96)])
+def test_outflow_mixed_refined_jet(shape):
+    pr = synth.jet_problem(*shape, seed=21, rho_l=640.0, rho_g=60.0, nmodes=5)
+    (got,), (rec,) = gpu_step([pr], precision=binding.PPE_PREC_MIXED, tol=1e-12, max_refine=3)
+    check(pr, got, rec, oracle_step(pr))
+    assert 1 <= rec["iters"] <= 3
+
+
+def test_outflow_batched_equals_single_bitwise():
+    probs = [synth.jet_problem(24, 16, 32, seed=300 + i, rho_l=100.0 * (3 + i)) for i in range(3)]
+    batched, brecs = gpu_step(probs, precision=binding.PPE_PREC_MIXED, max_refine=2)
+    for pr, b, br in zip(probs, batched, brecs):
+        (single,), (sr,) = gpu_step([pr], precision=binding.PPE_PREC_MIXED, max_refine=2)
+        for k in ("p", "u", "v", "w"):
+            assert np.array_equal(b[k], single[k]), k
+        assert br == sr

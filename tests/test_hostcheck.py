@@ -104,3 +104,27 @@ def test_tri_zero_mode_pin_and_gauge(hc, ny, P):
     assert np.abs(A @ x - rhs).max() < 1e-14 * np.abs(A).max() * np.abs(x).max()
     ls = np.linalg.lstsq(A, rhs, rcond=None)[0]
     assert np.abs(x - (ls - ls.mean())).max() < 1e-9 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("ny,P", [(2, 1), (3, 1), (5, 2), (8, 4), (64, 8), (128, 16), (255, 32), (100, 7)])
+@pytest.mark.parametrize("s", [0.0, 1e-6, 0.37, 25.0])
+def test_tri_outflow_top_matches_dense(hc, ny, P, s):
+    """Outflow top row: p = 0 on the top face, ghost -x_{ny-1}, so the last
+    diagonal entry is -3 - s; the system is regular even at s = 0."""
+    rng = np.random.default_rng(ny * 37 + P)
+    rhs = rng.standard_normal(ny) + 1j * rng.standard_normal(ny)
+    rin = np.ascontiguousarray(np.stack([rhs.real, rhs.imag], -1).ravel())
+    out = np.zeros(2 * ny)
+    assert hc.hc_tri(ny, P, s, 2, _p(rin), _p(out)) == 0
+    x = out[0::2] + 1j * out[1::2]
+    A = _dense(ny, s)
+    A[-1, -1] = -3.0 - s
+    want = np.linalg.solve(A, rhs)
+    cond = np.linalg.cond(A)
+    assert np.abs(x - want).max() <= 1e-15 * cond * np.abs(want).max() * 10
+
+
+def test_tri_rejects_pin_with_outflow(hc):
+    rin = np.zeros(16)
+    out = np.zeros(16)
+    assert hc.hc_tri(8, 2, 0.0, 3, _p(rin), _p(out)) == -1

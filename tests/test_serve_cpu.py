@@ -42,8 +42,8 @@ class FakeBackend(Backend):
     def plan_bytes(self, shape, batch):
         return self.plan_cost * batch
 
-    def make_plan(self, slot, shape, batch, lengths):
-        p = (slot, shape, batch, len(self.made))
+    def make_plan(self, slot, shape, batch, lengths, ybc=0):
+        p = (slot, shape, batch, len(self.made), tuple(lengths), ybc)
         self.made.append(p)
         return p
 
@@ -52,7 +52,7 @@ class FakeBackend(Backend):
 
     def launch(self, slot, plan, reqs):
         assert plan[1] == reqs[0].shape and plan[2] == len(reqs)
-        assert all(r.shape == reqs[0].shape for r in reqs)
+        assert all(r.plan_key == (plan[1], plan[4], plan[5]) for r in reqs)
         self.launches.append((slot, [r.rid for r in reqs]))
         work = sum(r.npts for r in reqs) / 1e6 * 1e-3
         return self.clock() + work
@@ -155,3 +155,19 @@ def test_grouping_helper_and_arrivals():
     a = poisson_arrivals(1000, 100.0, 1)
     assert a[0] == 0.0 and all(x <= y for x, y in zip(a, a[1:]))
     assert 8.0 < a[-1] < 12.0
+
+
+def test_boundaries_and_lengths_split_groups():
+    """Same shape but other y boundaries or lengths never share a plan or a launch."""
+    reqs = [mk(i, (32, 32, 32), 0.0) for i in range(6)]
+    reqs[1].ybc = 1
+    reqs[3].ybc = 1
+    reqs[4].lengths = (1.0, 1.0, 1.0)
+    srv, be, m = run(reqs, slots=1)
+    assert m["served"] == 6
+    keys = {(p[1], p[4], p[5]) for p in be.made}
+    assert len(keys) == 3
+    for _, rids in be.launches:
+        assert len({reqs[r].plan_key for r in rids}) == 1
+    groups = group_by_shape(reqs, 8)
+    assert sorted(len(g) for g in groups) == [1, 2, 3]
