@@ -48,9 +48,10 @@ Readings of points the paper leaves open (each is listed in the design notes):
     mean(b), and p is fixed by mean(p) = 0;
   * rho0 <= 0 requests rho0 = min(rho).
 
-Functions follow the paper's order: assemble the right-hand side (Eq. 29),
-solve the Poisson problem, project (Eq. 28).  The spectral solver diagonalises
-L completely (real FFT in x, complex FFT in z, DCT-II in y); the dense solver
+Functions follow the paper's order: the target divergence S (Eq. 26), the
+right-hand side (Eq. 29), the Poisson solve, the projection (Eq. 28).  The
+spectral solver diagonalises L completely (real FFT in x, complex FFT in z,
+DCT-II or DCT-IV in y); the dense solver
 factorises the bordered matrix with LAPACK.  Neither is the GPU's algorithm.
 """
 
@@ -77,6 +78,7 @@ __all__ = [
     "ppe_step",
     "solve_variable_coefficient_dense",
     "eigenvalues",
+    "source_term",
 ]
 
 
@@ -191,6 +193,36 @@ def eigenvalues(g: Grid):
         ly = -(4.0 / g.dy**2) * np.sin(np.pi * (2 * m + 1) / (4.0 * g.ny)) ** 2
     lz = -(4.0 / g.dz**2) * np.sin(np.pi * c / g.nz) ** 2
     return lz[:, None, None] + ly[None, :, None] + lx[None, None, :]
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5.4, Eq. (26): the target divergence S = div u^{n+1}
+# ---------------------------------------------------------------------------
+
+def source_term(C, div_g, div_l, mdot_area, area_density, rho_g, rho_l, under=None):
+    """S of Eq. (26), cell by cell.
+
+    With the phase-wise velocity divergences div_g = -(1/rho_g) D rho_g/Dt and
+    div_l = -(1/rho_l) D rho_l/Dt (the extrapolated compressibilities of
+    Sec. 4), Eq. (26) reads
+        S = (1 - C) div_g + C div_l + mdot (1/rho_g - 1/rho_l).
+    mdot = mdot' delta_Gamma (Sec. 3): mass flux per unit area times the
+    interface area density A_Gamma / V0, non-zero only in interface cells
+    0 < C < 1, where rho_g, rho_l are the interface densities (Sec. 5.4); the
+    phase-change term is not evaluated anywhere else, so those arrays are
+    never read outside interface cells.  Under-resolved interface cells (the
+    appendix on under-resolved regions) get S = 0; the mask has no effect on
+    single-phase cells.
+    """
+    C = np.asarray(C, dtype=np.float64)
+    S = (1.0 - C) * np.asarray(div_g, dtype=np.float64) + C * np.asarray(div_l, dtype=np.float64)
+    iface = (C > 0.0) & (C < 1.0)
+    mdot = np.asarray(mdot_area, dtype=np.float64)[iface] * np.asarray(area_density, dtype=np.float64)[iface]
+    S[iface] += mdot * (1.0 / np.asarray(rho_g, dtype=np.float64)[iface]
+                        - 1.0 / np.asarray(rho_l, dtype=np.float64)[iface])
+    if under is not None:
+        S[iface & (np.asarray(under) != 0)] = 0.0
+    return S
 
 
 # ---------------------------------------------------------------------------

@@ -311,3 +311,90 @@ def batch_48(seed=4000, count=48) -> List[Problem]:
     """48 independent requests of uneven sizes (same-shape ones share launches)."""
     shapes = batch_shapes(count, seed)
     return [mixed_instance(seed + 1 + i, shape=s) for i, s in enumerate(shapes)]
+
+
+# ---------------------------------------------------------------------------
+# Inputs of the target divergence S (Eq. 26): phase-wise compressibilities,
+# interface mass flux and area density, interface densities, under-resolved
+# mask.  The generator draws them; it does not form S.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Sources:
+    C: np.ndarray             # liquid volume fraction
+    div_g: np.ndarray         # gas-phase velocity divergence (extrapolated into the liquid band)
+    div_l: np.ndarray         # liquid-phase velocity divergence
+    mdot_area: np.ndarray     # interface mass flux per unit area (0 outside interface cells)
+    area_density: np.ndarray  # interface area per cell volume (0 outside interface cells)
+    rho_g: np.ndarray         # interface gas density (0 outside interface cells)
+    rho_l: np.ndarray         # interface liquid density (0 outside interface cells)
+    under: np.ndarray         # uint8, 1 in the under-resolved block
+
+    def fields(self):
+        return (self.C, self.div_g, self.div_l, self.mdot_area, self.area_density, self.rho_g, self.rho_l,
+                self.under)
+
+
+def smooth_field(rng, nx, ny, nz, lx, ly, lz, amp, nterms=6, kmax=3):
+    """amp * sum of separable cosine modes with N(0, 1) weights (no y boundary condition)."""
+    x = _centres(nx, lx)
+    y = _centres(ny, ly)
+    z = _centres(nz, lz)
+    f = np.zeros((nz, ny, nx))
+    for _ in range(nterms):
+        a, m, e = rng.integers(0, kmax + 1, size=3)
+        phx, phy, phz = rng.uniform(0, TWO_PI, size=3)
+        c = rng.standard_normal()
+        f += c * (np.cos(e * TWO_PI * z / lz + phz)[:, None, None]
+                  * np.cos(m * np.pi * y / ly + phy)[None, :, None]
+                  * np.cos(a * TWO_PI * x / lx + phx)[None, None, :])
+    return amp * f
+
+
+def interface_inputs(rng, C, lx, ly, lz, rho_l, rho_g, div_g_amp=1e-2, div_l_amp=1e-3, mdot_mean=0.3,
+                     mdot_sd=0.1, under_frac=0.125) -> Sources:
+    """Eq. (26) inputs around the interface described by C.
+
+    div_g, div_l: smooth fields of amplitude div_g_amp, div_l_amp everywhere
+    (the extrapolated compressibilities cover both phases' bands).  In
+    interface cells (0 < C < 1): m' ~ N(mdot_mean, mdot_sd^2) (vaporisation
+    positive), A/V0 = U(0.9, 1.3)/dy, rho_g(1 + U(-0.03, 0.03)),
+    rho_l(1 + U(-0.01, 0.01)); those four arrays are 0 elsewhere.  The
+    under-resolved mask flags the cells of one x-z block covering
+    under_frac of the x range and half of the z range, all y."""
+    nz, ny, nx = C.shape
+    dy = ly / ny
+    div_g = smooth_field(rng, nx, ny, nz, lx, ly, lz, div_g_amp)
+    div_l = smooth_field(rng, nx, ny, nz, lx, ly, lz, div_l_amp)
+    iface = (C > 0.0) & (C < 1.0)
+    n = int(iface.sum())
+    mdot = np.zeros(C.shape)
+    area = np.zeros(C.shape)
+    rg = np.zeros(C.shape)
+    rl = np.zeros(C.shape)
+    mdot[iface] = rng.normal(mdot_mean, mdot_sd, size=n)
+    area[iface] = rng.uniform(0.9, 1.3, size=n) / dy
+    rg[iface] = rho_g * (1.0 + rng.uniform(-0.03, 0.03, size=n))
+    rl[iface] = rho_l * (1.0 + rng.uniform(-0.01, 0.01, size=n))
+    under = np.zeros(C.shape, dtype=np.uint8)
+    wx = max(1, int(round(under_frac * nx)))
+    x0 = int(rng.integers(0, nx))
+    z0 = int(rng.integers(0, nz))
+    xs = (x0 + np.arange(wx)) % nx
+    zs = (z0 + np.arange(max(1, nz // 2))) % nz
+    under[np.ix_(zs, np.arange(ny), xs)] = 1
+    return Sources(C, div_g, div_l, mdot, area, rg, rl, under)
+
+
+def sheet_sources(nx, ny, nz, *, seed, rho_l=640.0, rho_g=100.0, h0=0.3, nmodes=3, lx=TWO_PI, ly=2.0,
+                  lz=TWO_PI) -> Sources:
+    """Eq. (26) inputs for the liquid sheet |y| < h0 + eta(x, z) of sheet_problem."""
+    rng = np.random.default_rng(seed)
+    modes = random_modes(rng, nmodes)
+    C = liquid_fraction(nx, ny, nz, lx, ly, lz, h0, modes)
+    return interface_inputs(rng, C, lx, ly, lz, rho_l, rho_g)
+
+
+def sources_256(seed=7000) -> Sources:
+    """256x128x256 sheet, rho 640/100: inputs of S."""
+    return sheet_sources(256, 128, 256, seed=seed)
