@@ -39,6 +39,10 @@ WORKLOADS = {
                                 "FP32 spectra + FP64 refinement to 1e-12, 512x256x512 sheet rho 640/60"),
     "sheet_512x256x512_fp64": ("sheet_512", 0, 0, "FP64 direct solve, 512x256x512 sheet rho 640/60"),
     "sheet_32_fp64": ("sheet_32", 0, 0, "FP64 direct solve, 32^3 sheet rho 640/100"),
+    "sheet_src_256x128x256_fp64": ("sheet_256", 0, 0,
+                                   "FP64: target divergence from Eq. (26) inputs (phase compressibilities, "
+                                   "interface mass flux, under-resolved block) + direct solve + correction, "
+                                   "256x128x256 liquid sheet rho 640/100"),
     "jet_256x128x256_fp64": ("jet_256", 0, 0, "FP64 direct solve, 256x128x256 half jet over a symmetry plane "
                                                "with an outflow (p = 0) top, rho 640/100"),
     "batch_48_mixed": ("batch_48", 1, 1, "48 independent sheets of uneven sizes {64^3, 96x64x96, 128x64x128, "
@@ -61,11 +65,13 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kernel: str, nx: int, ny: int, nz: int, precision: int, mode_update: bool = False) -> float:
+def algorithmic_bytes(kernel: str, nx: int, ny: int, nz: int, precision: int, mode_update: bool = False,
+                      n_iface: int = 0) -> float:
     """Bytes one launch must move for one instance (the compulsory traffic).
 
     N cells, Nv = nx (ny+1) nz v-faces, Ns = (nx/2+1) ny nz spectral values of
-    cs bytes (16 FP64, 8 FP32)."""
+    cs bytes (16 FP64, 8 FP32); n_iface interface cells (0 < C < 1) for the
+    target-divergence pass."""
     N = nx * ny * nz
     Nv = nx * (ny + 1) * nz
     Ns = (nx // 2 + 1) * ny * nz
@@ -79,6 +85,9 @@ def algorithmic_bytes(kernel: str, nx: int, ny: int, nz: int, precision: int, mo
         "k_c2r": cs * Ns + 8 * N + (8 * N if mode_update else 0),
         "k_resid": 3 * 8 * N,                          # b, p -> r
         "k_correct": 8 * (7 * N + Nv) + 8 * (2 * N + Nv),  # u*,v*,w*,rho,p^n,p^{n-1},p,S -> u,v,w
+        # C and one phase divergence -> S everywhere; interface cells also read
+        # the other divergence, m', A/V0, rho_g, rho_l (8 B each) and the mask (1 B)
+        "k_source": 24 * N + 41 * n_iface,
     }
     return float(table.get(kernel, 0.0))
 
@@ -262,6 +271,8 @@ def main():
 
     import torch
 
+    import numpy as np
+
     from paper_2103_01874_amd import binding, synth
 
     builder, precision, max_refine, desc = WORKLOADS[args.workload]
@@ -300,8 +311,21 @@ def main():
     torch.cuda.synchronize()
     g = lambda k: [fields[k]]
     o = lambda k: [outs[k]]
+    src_dev = None
+    n_iface = 0
+    if "_src_" in args.workload:
+        # Eq. (26) inputs around the same interface as the density field
+        rl, rg = pr.meta["rho_l"], pr.meta["rho_g"]
+        C = (pr.rho - rg) / (rl - rg)
+        src = synth.interface_inputs(np.random.default_rng(pr.meta["seed"] + 31), C, pr.lx, pr.ly, pr.lz, rl, rg)
+        n_iface = int(((src.C > 0) & (src.C < 1)).sum())
+        with torch.cuda.stream(stream):
+            src_dev = binding.sources_to_device(src, dev)
+        torch.cuda.synchronize()
 
     def one_step():
+        if src_dev is not None:
+            plan.source([src_dev], g("S"))
         plan.solve([pr.rho0], [pr.dt], g("us"), g("vs"), g("ws"), g("rho"), g("pn"), g("pnm1"), g("S"), o("p"),
                    info)
         plan.correct([pr.dt], g("us"), g("vs"), g("ws"), g("rho"), g("pn"), g("pnm1"), o("p"), g("S"), o("u"),
@@ -336,7 +360,7 @@ def main():
         dom = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
         kname, kv = dom
         per_launch = algorithmic_bytes(kname, pr.nx, pr.ny, pr.nz, precision,
-                                       mode_update=(kname == "k_c2r" and max_refine > 0))
+                                       mode_update=(kname == "k_c2r" and max_refine > 0), n_iface=n_iface)
         if kname == "k_c2r" and max_refine > 0:
             # half of the launches update p (read + write), half write it: average
             per_launch = 0.5 * (algorithmic_bytes(kname, pr.nx, pr.ny, pr.nz, precision, False)
@@ -346,6 +370,13 @@ def main():
         roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kname,
                     "avg_launch_us": kv["avg_us"], "bytes_per_launch": per_launch}
+        # every kernel's algorithmic rate, for the per-kernel view (k_c2r: mode 0 figure)
+        kernels_gbs = {}
+        for k, v in kernels.items():
+            bpl = algorithmic_bytes(k, pr.nx, pr.ny, pr.nz, precision, n_iface=n_iface)
+            if bpl > 0:
+                kernels_gbs[k] = round(bpl / (v["avg_us"] * 1e-6) / 1e9, 1)
+        roofline["kernels_gbs"] = kernels_gbs
         kernels = {k: round(v["avg_us"], 2) for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms"])}
 
     if args.copy_bytes > 0:

@@ -171,6 +171,43 @@ ppe_status_t ppe_correct(ppe_plan_t plan, const double* dt,
 ppe_status_t ppe_residual(ppe_plan_t plan, const double* const* u, const double* const* v,
                           const double* const* w, const double* const* S, double* out);
 
+/* Inputs of the target divergence S = div u^{n+1} of Eq. (26) (Sec. 5.4)
+ * for one instance: cell fields [nz][ny][nx], float64 device pointers owned
+ * by the caller.  C classifies each cell: gas (C <= 0), liquid (C >= 1),
+ * interface (0 < C < 1).
+ *   div_g, div_l : phase-wise velocity divergences -(1/rho_k) D rho_k/Dt (the
+ *                  extrapolated compressibilities, Sec. 4); div_g is read in
+ *                  gas and interface cells, div_l in liquid and interface
+ *                  cells
+ *   mdot         : interface mass flux per unit area m' (> 0 vaporisation)
+ *   area         : interface area density A_Gamma / V0 (Sec. 3: the
+ *                  phase-change rate per volume is m' A_Gamma / V0)
+ *   rho_g, rho_l : interface gas and liquid densities
+ *                  (mdot, area, rho_g, rho_l are read in interface cells only)
+ *   under        : uint8 mask, non-zero = under-resolved cell; an
+ *                  under-resolved interface cell gets S = 0 (the paper's
+ *                  treatment of under-resolved regions); NULL = no such cells */
+typedef struct {
+  const double* C;
+  const double* div_g;
+  const double* div_l;
+  const double* mdot;
+  const double* area;
+  const double* rho_g;
+  const double* rho_l;
+  const uint8_t* under;
+} ppe_source_t;
+
+/* Target divergence, Eq. (26):
+ *   gas cell S = div_g, liquid cell S = div_l, interface cell
+ *   S = (1 - C) div_g + C div_l + mdot * area * (1/rho_g - 1/rho_l)
+ *   (0 if under-resolved).
+ *   src : host array of `batch` records
+ *   S   : host array of `batch` device pointers (output, [nz][ny][nx]; must
+ *         not alias an input)
+ * The result is the S that ppe_solve and ppe_correct take. */
+ppe_status_t ppe_source(ppe_plan_t plan, const ppe_source_t* src, double* const* S);
+
 /* Per-kernel timing, for measurement tools.  With profiling enabled every
  * launch the plan makes is bracketed by two HIP events on the plan's stream;
  * durations are folded into per-kernel totals.  Enabling clears the totals.

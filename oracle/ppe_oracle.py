@@ -208,18 +208,30 @@ def source_term(C, div_g, div_l, mdot_area, area_density, rho_g, rho_l, under=No
         S = (1 - C) div_g + C div_l + mdot (1/rho_g - 1/rho_l).
     mdot = mdot' delta_Gamma (Sec. 3): mass flux per unit area times the
     interface area density A_Gamma / V0, non-zero only in interface cells
-    0 < C < 1, where rho_g, rho_l are the interface densities (Sec. 5.4); the
-    phase-change term is not evaluated anywhere else, so those arrays are
-    never read outside interface cells.  Under-resolved interface cells (the
-    appendix on under-resolved regions) get S = 0; the mask has no effect on
-    single-phase cells.
+    0 < C < 1, where rho_g, rho_l are the interface densities (Sec. 5.4).
+    Each phase's compressibility is extrapolated only into a thin band across
+    the interface (Sec. 4), and away from it Eq. (26) reduces to the
+    compressibility of the phase present (the remark after Eq. 26): a gas
+    cell (C <= 0) takes div_g, a liquid cell (C >= 1) div_l, and neither
+    reads the other phase's value; the phase-change arrays are read in
+    interface cells only.  Under-resolved interface cells (the appendix on
+    under-resolved regions) get S = 0; the mask has no effect on single-phase
+    cells.
     """
     C = np.asarray(C, dtype=np.float64)
-    S = (1.0 - C) * np.asarray(div_g, dtype=np.float64) + C * np.asarray(div_l, dtype=np.float64)
-    iface = (C > 0.0) & (C < 1.0)
+    div_g = np.asarray(div_g, dtype=np.float64)
+    div_l = np.asarray(div_l, dtype=np.float64)
+    gas = C <= 0.0
+    liq = C >= 1.0
+    iface = ~gas & ~liq
+    S = np.zeros(C.shape)
+    S[gas] = div_g[gas]
+    S[liq] = div_l[liq]
+    c = C[iface]
     mdot = np.asarray(mdot_area, dtype=np.float64)[iface] * np.asarray(area_density, dtype=np.float64)[iface]
-    S[iface] += mdot * (1.0 / np.asarray(rho_g, dtype=np.float64)[iface]
-                        - 1.0 / np.asarray(rho_l, dtype=np.float64)[iface])
+    S[iface] = ((1.0 - c) * div_g[iface] + c * div_l[iface]
+                + mdot * (1.0 / np.asarray(rho_g, dtype=np.float64)[iface]
+                          - 1.0 / np.asarray(rho_l, dtype=np.float64)[iface]))
     if under is not None:
         S[iface & (np.asarray(under) != 0)] = 0.0
     return S

@@ -21,6 +21,8 @@ PPE_PREC_FP64 = 0
 PPE_PREC_MIXED = 1
 PPE_YBC_WALLS = 0
 PPE_YBC_OUTFLOW = 1
+PPE_OK = 0
+PPE_ERR_ARG = -1
 MAX_BATCH = 64
 
 STATUS = {0: "ok", -1: "bad argument", -2: "out of memory", -3: "device error", -4: "not converged",
@@ -47,7 +49,15 @@ INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("rho0_used", "<f8")
 assert INFO_DTYPE.itemsize == 64
 
 EXPORTS = ["ppe_plan_workspace_bytes", "ppe_plan", "ppe_plan_destroy", "ppe_plan_set_stream", "ppe_solve",
-           "ppe_correct", "ppe_residual", "ppe_plan_profile", "ppe_plan_profile_read", "ppe_version"]
+           "ppe_correct", "ppe_residual", "ppe_source", "ppe_plan_profile", "ppe_plan_profile_read",
+           "ppe_version"]
+
+SOURCE_FIELDS = ("C", "div_g", "div_l", "mdot", "area", "rho_g", "rho_l")
+
+
+class Source(ctypes.Structure):
+    """ppe_source_t: device pointers of the Eq. (26) inputs of one instance."""
+    _fields_ = [(k, ctypes.c_void_p) for k in SOURCE_FIELDS] + [("under", ctypes.c_void_p)]
 
 
 class KernelTime(ctypes.Structure):
@@ -87,6 +97,8 @@ def load(path: str = LIB_PATH):
     lib.ppe_correct.restype = ctypes.c_int
     lib.ppe_residual.argtypes = [P, PP, PP, PP, PP, P]
     lib.ppe_residual.restype = ctypes.c_int
+    lib.ppe_source.argtypes = [P, ctypes.POINTER(Source), PP]
+    lib.ppe_source.restype = ctypes.c_int
     lib.ppe_plan_profile.argtypes = [P, ctypes.c_int32]
     lib.ppe_plan_profile.restype = ctypes.c_int
     lib.ppe_plan_profile_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_int32,
@@ -238,6 +250,30 @@ class Plan:
         _check(st, "ppe_correct")
         return info
 
+    def source(self, srcs: Sequence[Dict], S):
+        """ppe_source: S[i] from the Eq. (26) inputs srcs[i] (dicts of float64
+        cell tensors named as SOURCE_FIELDS, plus an optional uint8 'under')."""
+        torch = self._torch
+        if len(srcs) != self.batch:
+            raise PPEError(f"sources: expected {self.batch} records, got {len(srcs)}")
+        recs = (Source * self.batch)()
+        for i, d in enumerate(srcs):
+            for k in SOURCE_FIELDS:
+                if d.get(k) is None:
+                    raise PPEError(f"sources[{i}]: missing {k}")
+                setattr(recs[i], k, self._cell(d[k], f"{k}[{i}]").data_ptr())
+            m = d.get("under")
+            if m is not None:
+                if not isinstance(m, torch.Tensor) or m.dtype != torch.uint8 or m.device != self.device \
+                        or tuple(m.shape) != (self.nz, self.ny, self.nx) or not m.is_contiguous():
+                    raise PPEError(f"under[{i}]: expected contiguous uint8 cell tensor on {self.device}")
+                recs[i].under = m.data_ptr()
+            else:
+                recs[i].under = None
+        outs = self._batch(S, "S")
+        _check(self.lib.ppe_source(self._h, recs, _ptrs(outs)), "ppe_source")
+        return S
+
     def residual(self, u, v, w, S, out=None):
         """ppe_residual: per instance (||d - mean d||_2, max|d - mean d|, mean d), d = D u - S."""
         torch = self._torch
@@ -255,6 +291,15 @@ def to_device(problem, device="cuda"):
 
     return {k: torch.from_numpy(np.ascontiguousarray(getattr(problem, k))).to(device)
             for k in ("us", "vs", "ws", "rho", "pn", "pnm1", "S")}
+
+
+def sources_to_device(src, device="cuda") -> Dict:
+    """Copy a synth.Sources' fields to the device under the binding's names."""
+    import torch
+
+    names = {"C": "C", "div_g": "div_g", "div_l": "div_l", "mdot": "mdot_area", "area": "area_density",
+             "rho_g": "rho_g", "rho_l": "rho_l", "under": "under"}
+    return {k: torch.from_numpy(np.ascontiguousarray(getattr(src, v))).to(device) for k, v in names.items()}
 
 
 def step(plan: Plan, fields: List[Dict], rho0, dt, outputs: Optional[List[Dict]] = None, info=None):

@@ -15,6 +15,8 @@
 //   k_residual   FP64 r = b - L p fused with the real FFT of r (refinement)
 //   k_correct    u^{n+1} = u* - dt[G p/rho0 + gamma_f G p_hat]  (Eq. 28) and
 //                the continuity residual of the result
+// and, before a solve when the caller assembles S through the library:
+//   k_source     S = (1-C) div_g + C div_l + m' (A/V0)(1/rho_g - 1/rho_l)  (Eq. 26)
 #pragma once
 
 #include "ppe_device.hpp"
@@ -94,6 +96,23 @@ struct Work {
   const double* lamx;   // [hx]  lam_x(kx)
   const double* lamz;   // [nz]  lam_z(kz)
   int inst0;            // first instance of this launch in the workspace
+};
+
+// Inputs and output of the target-divergence pass (Eq. 26) for one instance.
+struct SrcPtrs {
+  const double* C;
+  const double* div_g;
+  const double* div_l;
+  const double* mdot;
+  const double* area;
+  const double* rho_g;
+  const double* rho_l;
+  const uint8_t* under;   // may be null
+  double* S;
+};
+
+struct SrcTable {
+  SrcPtrs in[kMaxLaunch];
 };
 
 // ppe_info_t as laid out in include/ppe.h

@@ -689,6 +689,39 @@ ppe_status_t ppe_residual(ppe_plan_t p, const double* const* u, const double* co
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
 }
 
+ppe_status_t ppe_source(ppe_plan_t p, const ppe_source_t* src, double* const* S) {
+  if (!p || !src || !S) return PPE_ERR_ARG;
+  const int B = p->d.batch;
+  for (int i = 0; i < B; ++i) {
+    const ppe_source_t& q = src[i];
+    if (!q.C || !q.div_g || !q.div_l || !q.mdot || !q.area || !q.rho_g || !q.rho_l || !S[i]) return PPE_ERR_ARG;
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
+  const long long n = p->g.npts;
+  const long long per_block = (long long)kSrcPT * kSrcThreads;
+  const unsigned blocks = (unsigned)((n + per_block - 1) / per_block);
+  for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
+    const int nb = std::min(kMaxLaunch, B - i0);
+    SrcTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    for (int i = 0; i < nb; ++i) {
+      const ppe_source_t& q = src[i0 + i];
+      SrcPtrs& t = tab.in[i];
+      t.C = q.C;
+      t.div_g = q.div_g;
+      t.div_l = q.div_l;
+      t.mdot = q.mdot;
+      t.area = q.area;
+      t.rho_g = q.rho_g;
+      t.rho_l = q.rho_l;
+      t.under = q.under;
+      t.S = S[i0 + i];
+    }
+    PPE_TIMED(p, "k_source", (k_source<<<dim3(blocks, 1, nb), kSrcThreads, 0, p->stream>>>(tab, n)));
+  }
+  return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
+}
+
 ppe_status_t ppe_plan_profile(ppe_plan_t p, int32_t enable) {
   if (!p) return PPE_ERR_ARG;
   if (enable) {

@@ -1,0 +1,154 @@
+"""GPU parity of the target-divergence pass (Eq. 26) against the oracle.
+
+Single-phase and under-resolved cells are copies or zeros: bit-exact.  An
+interface cell adds three products in FP64; the kernel may contract them
+into fused multiply-adds, so it is held to 4 ulp of the sum of the terms'
+magnitudes.  Arrays the method never reads in a cell (the other phase's
+divergence, the phase-change fields away from the interface) hold NaN there.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2103_01874_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+ULP = 2.0 ** -52
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def planted(shape, seed):
+    rng = np.random.default_rng(seed)
+    C = rng.choice([0.0, 1.0, 0.5], size=shape, p=[0.4, 0.4, 0.2])
+    C[C == 0.5] = rng.uniform(1e-6, 1 - 1e-6, size=int((C == 0.5).sum()))
+    iface = (C > 0) & (C < 1)
+    d = {"C": C, "div_g": rng.standard_normal(shape), "div_l": 0.1 * rng.standard_normal(shape)}
+    d["div_g"][C == 1.0] = np.nan
+    d["div_l"][C == 0.0] = np.nan
+    for k, lo, hi in (("mdot", 0.05, 1.0), ("area", 5.0, 40.0), ("rho_g", 50.0, 150.0), ("rho_l", 500.0, 800.0)):
+        a = np.full(shape, np.nan)
+        a[iface] = rng.uniform(lo, hi, size=int(iface.sum()))
+        d[k] = a
+    d["under"] = (rng.uniform(size=shape) < 0.25).astype(np.uint8)
+    return d
+
+
+def oracle_S(d, with_mask=True):
+    return O.source_term(d["C"], d["div_g"], d["div_l"], d["mdot"], d["area"], d["rho_g"], d["rho_l"],
+                         d["under"] if with_mask else None)
+
+
+def gpu_S(shape, dicts, with_mask=True):
+    torch = _torch()
+    nx, ny, nz = shape[2], shape[1], shape[0]
+    plan = binding.Plan(nx, ny, nz, batch=len(dicts))
+    dev = []
+    for d in dicts:
+        t = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in d.items()}
+        if not with_mask:
+            t["under"] = None
+        dev.append(t)
+    S = [torch.empty(shape, dtype=torch.float64, device="cuda") for _ in dicts]
+    plan.source(dev, S)
+    torch.cuda.synchronize()
+    plan.close()
+    return [s.cpu().numpy() for s in S]
+
+
+def check(d, got, with_mask=True):
+    ref = oracle_S(d, with_mask)
+    C = d["C"]
+    iface = (C > 0) & (C < 1)
+    assert np.all(np.isfinite(got))
+    single = ~iface
+    assert np.array_equal(got[single], ref[single])
+    if with_mask:
+        m = iface & (d["under"] != 0)
+        assert np.all(got[m] == 0.0)
+    c = C[iface]
+    scale = (np.abs((1 - c) * d["div_g"][iface]) + np.abs(c * d["div_l"][iface])
+             + np.abs(d["mdot"][iface] * d["area"][iface]) * (1 / d["rho_g"][iface] + 1 / d["rho_l"][iface]))
+    err = np.abs(got[iface] - ref[iface])
+    assert np.all(err <= 4 * ULP * scale), float((err / scale).max())
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 6), (9, 5, 8), (16, 32, 64), (27, 33, 48)])
+def test_source_matches_oracle_planted_garbage(shape):
+    d = planted(shape, sum(shape))
+    (got,) = gpu_S(shape, [d])
+    check(d, got)
+
+
+def test_source_without_mask_and_batched():
+    shape = (6, 10, 12)
+    ds = [planted(shape, 40 + i) for i in range(3)]
+    got = gpu_S(shape, ds, with_mask=False)
+    for d, g in zip(ds, got):
+        check(d, g, with_mask=False)
+    # batched result equals each instance alone, bitwise
+    for d, g in zip(ds, got):
+        (alone,) = gpu_S(shape, [d], with_mask=False)
+        assert np.array_equal(alone, g)
+
+
+def test_source_sheet_256x128x256_every_point():
+    s = synth.sources_256()
+    d = {"C": s.C, "div_g": s.div_g, "div_l": s.div_l, "mdot": s.mdot_area, "area": s.area_density,
+         "rho_g": s.rho_g, "rho_l": s.rho_l, "under": s.under}
+    (got,) = gpu_S(s.C.shape, [d])
+    check(d, got)
+
+
+def test_source_then_projection_matches_oracle_chain():
+    """Eq. (26) -> Eq. (29) -> Eq. (28) on the GPU against the same chain in
+    the oracle, walls and outflow top."""
+    torch = _torch()
+    for ybc in (0, 1):
+        pr = synth.sheet_problem(48, 32, 36, seed=77, nmodes=3) if ybc == 0 else \
+            synth.jet_problem(48, 32, 36, seed=78, nmodes=3)
+        rl, rg = pr.meta["rho_l"], pr.meta["rho_g"]
+        C = (pr.rho - rg) / (rl - rg)   # the generator's own density-fraction relation
+        src = synth.interface_inputs(np.random.default_rng(80 + ybc), C, pr.lx, pr.ly, pr.lz, rl, rg)
+        S_o = O.source_term(*src.fields())
+        g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=ybc)
+        ref = O.ppe_step(g, pr.rho0, pr.dt, pr.us, pr.vs, pr.ws, pr.rho, pr.pn, pr.pnm1, S_o)
+        plan = binding.Plan(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=ybc)
+        f = binding.to_device(pr)
+        sd = binding.sources_to_device(src)
+        S = torch.empty_like(f["rho"])
+        plan.source([sd], [S])
+        f["S"] = S
+        outs, info = binding.step(plan, [f], [pr.rho0], [pr.dt])
+        torch.cuda.synchronize()
+        rec = binding.decode_info(info)[0]
+        p = outs[0]["p"].cpu().numpy()
+        v = outs[0]["v"].cpu().numpy()
+        rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+        print(f"ybc={ybc} eps_p={rel(p, ref['p']):.2e} eps_v={rel(v - pr.vs, ref['v'] - pr.vs):.2e} "
+              f"eps_div={rec['res_rel']:.2e}", flush=True)
+        assert rec["status"] == 0
+        assert rel(p, ref["p"]) <= 1e-12
+        assert rel(v - pr.vs, ref["v"] - pr.vs) <= 1e-12
+        assert rec["res_rel"] <= 1e-12
+        plan.close()
+
+
+def test_source_argument_errors():
+    torch = _torch()
+    plan = binding.Plan(8, 4, 8)
+    d = {k: torch.zeros((8, 4, 8), dtype=torch.float64, device="cuda") for k in binding.SOURCE_FIELDS}
+    S = torch.empty((8, 4, 8), dtype=torch.float64, device="cuda")
+    rec = (binding.Source * 1)()
+    for k in binding.SOURCE_FIELDS:
+        setattr(rec[0], k, d[k].data_ptr())
+    rec[0].C = None
+    arr = (binding.ctypes.c_void_p * 1)(S.data_ptr())
+    assert plan.lib.ppe_source(plan._h, rec, arr) == binding.PPE_ERR_ARG
+    with pytest.raises(binding.PPEError):
+        plan.source([{k: v for k, v in d.items() if k != "rho_l"}], [S])
+    plan.close()

@@ -25,13 +25,16 @@ from paper_2103_01874_amd import synth
 
 def random_inputs(shape, seed, garbage=np.nan):
     """Fields of the given shape; the interface-only arrays hold `garbage`
-    outside interface cells, to show they are never read there."""
+    outside interface cells, and each phase's divergence holds it in the cells
+    of the other phase, to show they are never read there."""
     rng = np.random.default_rng(seed)
     C = rng.choice([0.0, 1.0, 0.5], size=shape, p=[0.4, 0.4, 0.2])
     C[C == 0.5] = rng.uniform(0.01, 0.99, size=int((C == 0.5).sum()))
     iface = (C > 0) & (C < 1)
     div_g = rng.standard_normal(shape)
     div_l = rng.standard_normal(shape)
+    div_g[C == 1.0] = garbage   # undefined away from the band: never read
+    div_l[C == 0.0] = garbage
     arrs = []
     for lo, hi in ((0.1, 1.0), (5.0, 20.0), (50.0, 150.0), (500.0, 800.0)):
         a = np.full(shape, garbage)
