@@ -63,6 +63,8 @@ struct ppe_plan_s {
   int tx = 1;            // kx columns per block (z FFT)
   int txs = 1, pch = 1;  // systems per block, chunks per system (tri)
   int mc = 16;           // register rows per chunk (template of k_tri)
+  int src_pt = 8;        // units per thread of k_source (2, 4 or 8)
+  int src_vec = 2;       // cells per unit of k_source (1, or 2 when aligned)
   size_t lds_x = 0, lds_z = 0, lds_t = 0;
   // z-marching stencil tiles, one shape per kernel
   struct MarchCfg {
@@ -209,6 +211,11 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   p->mc = mmax <= 4 ? 4 : (mmax <= 8 ? 8 : 16);
   p->lds_t = std::max((size_t)p->txs * 2 * P * sizeof(RedRow<double>), (size_t)p->txs * P * 8);
   if (p->lds_x > 65536 || p->lds_z > lds_limit || p->lds_t > 65536) return false;
+  // target-divergence pass
+  if (tune_env("PPE_TUNE_SRC_PT") > 0) p->src_pt = tune_env("PPE_TUNE_SRC_PT");
+  if (tune_env("PPE_TUNE_SRC_VEC") > 0) p->src_vec = tune_env("PPE_TUNE_SRC_VEC");
+  if (p->src_pt != 2 && p->src_pt != 4) p->src_pt = 8;
+  if (p->src_vec != 1) p->src_vec = 2;
   // z-marching stencils: TXT x TJ tiles (TXT a divisor of nx, <= 128), KC planes
   // per chunk; the tile height per kernel trades halo traffic against registers
   if (!march_shape(d, 256, 64, "PPE_TUNE_TJ_RHS", p->mrhs) || !march_shape(d, 256, 64, "PPE_TUNE_TJ_COR", p->mcor) ||
@@ -698,8 +705,18 @@ ppe_status_t ppe_source(ppe_plan_t p, const ppe_source_t* src, double* const* S)
   }
   if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
   const long long n = p->g.npts;
-  const long long per_block = (long long)kSrcPT * kSrcThreads;
-  const unsigned blocks = (unsigned)((n + per_block - 1) / per_block);
+  // paired 16-byte accesses when every array of the call is 16-byte aligned
+  bool aligned = true;
+  auto al = [&](const void* q) { aligned = aligned && (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  for (int i = 0; i < B; ++i) {
+    const ppe_source_t& q = src[i];
+    al(q.C), al(q.div_g), al(q.div_l), al(q.mdot), al(q.area), al(q.rho_g), al(q.rho_l), al(S[i]);
+  }
+  const int vec = (aligned && p->src_vec == 2) ? 2 : 1;
+  const int pt = p->src_pt;
+  const long long units = vec == 2 ? std::max(1LL, n >> 1) : n;
+  const long long per_block = (long long)pt * kSrcThreads;
+  const unsigned blocks = (unsigned)((units + per_block - 1) / per_block);
   for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
     const int nb = std::min(kMaxLaunch, B - i0);
     SrcTable tab;
@@ -717,7 +734,18 @@ ppe_status_t ppe_source(ppe_plan_t p, const ppe_source_t* src, double* const* S)
       t.under = q.under;
       t.S = S[i0 + i];
     }
-    PPE_TIMED(p, "k_source", (k_source<<<dim3(blocks, 1, nb), kSrcThreads, 0, p->stream>>>(tab, n)));
+#define PPE_SRC_LAUNCH(PTV, VV) \
+  (k_source<PTV, VV><<<dim3(blocks, 1, nb), kSrcThreads, 0, p->stream>>>(tab, n))
+    if (vec == 2) {
+      if (pt == 2) PPE_TIMED(p, "k_source", PPE_SRC_LAUNCH(2, 2));
+      else if (pt == 4) PPE_TIMED(p, "k_source", PPE_SRC_LAUNCH(4, 2));
+      else PPE_TIMED(p, "k_source", PPE_SRC_LAUNCH(8, 2));
+    } else {
+      if (pt == 2) PPE_TIMED(p, "k_source", PPE_SRC_LAUNCH(2, 1));
+      else if (pt == 4) PPE_TIMED(p, "k_source", PPE_SRC_LAUNCH(4, 1));
+      else PPE_TIMED(p, "k_source", PPE_SRC_LAUNCH(8, 1));
+    }
+#undef PPE_SRC_LAUNCH
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
 }
