@@ -77,7 +77,7 @@ def check(d, got, with_mask=True):
     assert np.all(err <= 4 * ULP * scale), float((err / scale).max())
 
 
-@pytest.mark.parametrize("shape", [(3, 4, 6), (9, 5, 8), (16, 32, 64), (27, 33, 48)])
+@pytest.mark.parametrize("shape", [(3, 4, 6), (9, 5, 8), (16, 32, 64), (27, 33, 48), (3, 5, 9), (9, 7, 27)])
 def test_source_matches_oracle_planted_garbage(shape):
     d = planted(shape, sum(shape))
     (got,) = gpu_S(shape, [d])
@@ -94,6 +94,31 @@ def test_source_without_mask_and_batched():
     for d, g in zip(ds, got):
         (alone,) = gpu_S(shape, [d], with_mask=False)
         assert np.array_equal(alone, g)
+
+
+def test_source_unaligned_views_take_the_single_cell_path():
+    """Arrays offset by one double (8-byte aligned only) give the same S."""
+    torch = _torch()
+    shape = (9, 7, 27)   # odd cell count
+    d = planted(shape, 91)
+    ref = gpu_S(shape, [d])[0]
+    n = int(np.prod(shape))
+    plan = binding.Plan(shape[2], shape[1], shape[0])
+    t = {}
+    for k, v in d.items():
+        dt = torch.uint8 if k == "under" else torch.float64
+        big = torch.zeros(n + 1, dtype=dt, device="cuda")
+        big[1:] = torch.from_numpy(np.ascontiguousarray(v).ravel()).cuda()
+        t[k] = big[1:].view(shape)
+    Sbig = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    S = Sbig[1:].view(shape)
+    assert S.data_ptr() % 16 == 8
+    plan.source([t], [S])
+    torch.cuda.synchronize()
+    got = S.cpu().numpy()
+    plan.close()
+    assert np.array_equal(got, ref)
+    check(d, got)
 
 
 def test_source_sheet_256x128x256_every_point():
