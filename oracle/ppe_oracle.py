@@ -79,6 +79,10 @@ __all__ = [
     "solve_variable_coefficient_dense",
     "eigenvalues",
     "source_term",
+    "variable_coefficient_operator",
+    "energy_norm",
+    "split_map",
+    "split_fixed_point",
 ]
 
 
@@ -415,3 +419,64 @@ def solve_variable_coefficient_dense(g: Grid, dt, us, vs, ws, rho, S):
     rhs = np.zeros(n + 1)
     rhs[:n] = rhs_c.ravel()
     return np.linalg.solve(M, rhs)[:n].reshape(g.shape)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5.4: the split as a map p_hat -> p, its fixed point (the pressure of
+# Eq. 25) and how far one split solve is from it
+# ---------------------------------------------------------------------------
+
+def variable_coefficient_operator(g: Grid, rho, p):
+    """A p = D((1/rho_f) G p): the operator of Eq. (25)."""
+    rx, ry, rz = face_density(rho)
+    gx, gy, gz = gradient(g, p)
+    return divergence(g, gx / rx, gy / ry, gz / rz)
+
+
+def energy_norm(g: Grid, e):
+    """||e||_E = sqrt(-e . L e), the norm in which the split map contracts."""
+    e = np.asarray(e, dtype=np.float64)
+    return float(np.sqrt(max(-np.sum(e * laplacian(g, e)), 0.0)))
+
+
+def split_map(g: Grid, rho0, dt, us, vs, ws, rho, S, ph, workers=None):
+    """F(p_hat): the split solve (Eqs. 27-29) with p^n = p^{n-1} = p_hat."""
+    p, _, _ = solve(g, rho0, dt, us, vs, ws, rho, ph, ph, S, workers=workers)
+    return p
+
+
+def split_fixed_point(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, S, iters, tol=0.0, workers=None):
+    """Iterate p_{k+1} = F(p_k) from p_0 = 2 p^n - p^{n-1}.
+
+    Sec. 5.4 states the split is exact when grad p_hat equals grad p^{n+1}: a
+    fixed point of F is the pressure of Eq. (25) (zero mean with zero-flux y
+    ends).  p_1 is the ordinary split solve.  For each iterate the relative
+    residual of Eq. (25),
+        res_k = ||rho0 [(1/dt)(D u* - S_c) - A p_k]||_2 / ||(rho0/dt)(D u* - S_c)||_2,
+    is recorded (res_0 belongs to p_0 = p_hat); iteration stops once
+    res_k <= tol or after `iters` maps.  Returns dict(p, iters, res, upd_E)
+    with upd_E[k] = ||p_{k+1} - p_k||_E.
+    """
+    r0 = rho0_of(rho, rho0)
+    d0 = divergence(g, us, vs, ws) - S
+    if g.ybc == 0:
+        d0 = d0 - np.mean(d0)
+    ref = float(np.linalg.norm((r0 / dt) * d0))
+    p = p_hat(pn, pnm1)
+    res, upd = [], []
+
+    def residual(q):
+        r = r0 * (d0 / dt - variable_coefficient_operator(g, rho, q))
+        if g.ybc == 0:
+            r = r - np.mean(r)
+        return float(np.linalg.norm(r)) / ref if ref > 0 else float(np.linalg.norm(r))
+
+    res.append(residual(p))
+    k = 0
+    while k < iters and res[-1] > tol:
+        q = split_map(g, r0, dt, us, vs, ws, rho, S, p, workers=workers)
+        upd.append(energy_norm(g, q - p))
+        p = q
+        k += 1
+        res.append(residual(p))
+    return {"p": p, "iters": k, "res": res, "upd_E": upd, "rho0": r0}
