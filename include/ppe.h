@@ -82,6 +82,11 @@ typedef enum {
                           plane), p = 0 on the top face (outflow) */
 } ppe_ybc_t;
 
+/* Plan options (ppe_desc_t.flags). */
+#define PPE_FLAG_VARCOEF 1   /* also allocate the FP64 residual buffer that
+                                ppe_solve_varcoef needs (always present for
+                                PPE_PREC_MIXED): 8 bytes per cell and instance */
+
 /* Precision of the spectral passes (FFTs and tridiagonal sweeps). */
 typedef enum {
   PPE_PREC_FP64 = 0,   /* FP64 storage and arithmetic: the direct solve */
@@ -101,6 +106,8 @@ typedef struct {
   int32_t max_refine;      /* PPE_PREC_MIXED: refinement sweeps after the first
                               solve (>= 0) */
   int32_t batch;           /* same-shape instances handled per call (>= 1) */
+  int32_t flags;           /* PPE_FLAG_* */
+  int32_t reserved;        /* 0 */
 } ppe_desc_t;
 
 /* Per-instance record, written to DEVICE memory by ppe_solve / ppe_correct. */
@@ -150,6 +157,37 @@ ppe_status_t ppe_solve(ppe_plan_t plan, const double* rho0, const double* dt,
                        const double* const* us, const double* const* vs, const double* const* ws,
                        const double* const* rho, const double* const* pn, const double* const* pnm1,
                        const double* const* S, double* const* p, ppe_info_t* info);
+
+/* Pressure of the variable-coefficient problem, Eq. (25), by the split
+ * fixed-point iteration (Sec. 5.4: the split is exact when grad p_hat equals
+ * grad p^{n+1}, so the pressure of Eq. 25 is the fixed point of the split
+ * with p_hat fed back):
+ *   p_0 = 2 p^n - p^{n-1},
+ *   p_{k+1} = p_k + L^+ [ (rho0/dt)(D u* - S) - rho0 D((1/rho_f) G p_k) ],
+ * where the bracket is rho0 times the residual of Eq. (25) (in FP64) and L^+
+ * the same FFT/tridiagonal solve as ppe_solve (in the plan's precision), with
+ * the same compatibility and gauge.  p_1 is exactly ppe_solve's pressure.
+ * The error contracts at least by 1 - rho0/rho_max per sweep (energy norm), so
+ * the first update also bounds the split's own error:
+ *   ||p_1 - q||_E <= ||p_2 - p_1||_E / (rho0/rho_max).
+ * Stops when the relative residual
+ *   res_k = ||rho0 [(1/dt)(D u* - S_c) - D((1/rho_f) G p_k)]||_2 / ||(rho0/dt)(D u* - S_c)||_2
+ * reaches tol, or after max_iters updates (>= 0; 0 only evaluates res_0).
+ * The plan needs PPE_FLAG_VARCOEF or PPE_PREC_MIXED (else PPE_ERR_ARG).
+ *   p     : output, must not alias p^n or p^{n-1}
+ *   info  : status (PPE_ERR_NOT_CONVERGED if res > tol after max_iters, or
+ *           NONFINITE), iters = updates applied, res_rel = last residual,
+ *           rho0_used, compat_defect
+ *   hist  : NULL or a device array [batch][max_iters + 1]; hist[b][k] = res_k,
+ *           -1 after convergence
+ * ppe_correct(pn = p, pnm1 = p, p) then applies the variable-density
+ * projection u^{n+1} = u* - dt G p / rho_f, whose relative divergence error
+ * is the last res. */
+ppe_status_t ppe_solve_varcoef(ppe_plan_t plan, const double* rho0, const double* dt,
+                               const double* const* us, const double* const* vs, const double* const* ws,
+                               const double* const* rho, const double* const* pn, const double* const* pnm1,
+                               const double* const* S, double* const* p, ppe_info_t* info,
+                               int32_t max_iters, double tol, double* hist);
 
 /* Projection, Eq. (28) (Sec. 5.4), and the continuity check of the result.
  * Reads rho0_used and compat_defect from `info` (as written by ppe_solve for

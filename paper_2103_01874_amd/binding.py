@@ -21,8 +21,10 @@ PPE_PREC_FP64 = 0
 PPE_PREC_MIXED = 1
 PPE_YBC_WALLS = 0
 PPE_YBC_OUTFLOW = 1
+PPE_FLAG_VARCOEF = 1
 PPE_OK = 0
 PPE_ERR_ARG = -1
+PPE_ERR_NOT_CONVERGED = -4
 MAX_BATCH = 64
 
 STATUS = {0: "ok", -1: "bad argument", -2: "out of memory", -3: "device error", -4: "not converged",
@@ -37,10 +39,11 @@ class Desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("ybc", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_refine", ctypes.c_int32), ("batch", ctypes.c_int32)]
+                ("max_refine", ctypes.c_int32), ("batch", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
-assert ctypes.sizeof(Desc) == 64
+assert ctypes.sizeof(Desc) == 72
 
 
 INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("rho0_used", "<f8"), ("compat_defect", "<f8"),
@@ -49,8 +52,8 @@ INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("rho0_used", "<f8")
 assert INFO_DTYPE.itemsize == 64
 
 EXPORTS = ["ppe_plan_workspace_bytes", "ppe_plan", "ppe_plan_destroy", "ppe_plan_set_stream", "ppe_solve",
-           "ppe_correct", "ppe_residual", "ppe_source", "ppe_plan_profile", "ppe_plan_profile_read",
-           "ppe_version"]
+           "ppe_correct", "ppe_residual", "ppe_source", "ppe_solve_varcoef", "ppe_plan_profile",
+           "ppe_plan_profile_read", "ppe_version"]
 
 SOURCE_FIELDS = ("C", "div_g", "div_l", "mdot", "area", "rho_g", "rho_l")
 
@@ -99,6 +102,9 @@ def load(path: str = LIB_PATH):
     lib.ppe_residual.restype = ctypes.c_int
     lib.ppe_source.argtypes = [P, ctypes.POINTER(Source), PP]
     lib.ppe_source.restype = ctypes.c_int
+    lib.ppe_solve_varcoef.argtypes = [P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, P, ctypes.c_int32, ctypes.c_double,
+                                      P]
+    lib.ppe_solve_varcoef.restype = ctypes.c_int
     lib.ppe_plan_profile.argtypes = [P, ctypes.c_int32]
     lib.ppe_plan_profile.restype = ctypes.c_int
     lib.ppe_plan_profile_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_int32,
@@ -111,9 +117,9 @@ def load(path: str = LIB_PATH):
 
 
 def make_desc(nx, ny, nz, lx=2 * np.pi, ly=2.0, lz=2 * np.pi, precision=PPE_PREC_FP64, tol=1e-12,
-              max_refine=1, batch=1, ybc=PPE_YBC_WALLS) -> Desc:
+              max_refine=1, batch=1, ybc=PPE_YBC_WALLS, flags=0) -> Desc:
     return Desc(int(nx), int(ny), int(nz), float(lx), float(ly), float(lz), int(precision), int(ybc),
-                float(tol), int(max_refine), int(batch))
+                float(tol), int(max_refine), int(batch), int(flags), 0)
 
 
 def workspace_bytes(desc: Desc) -> int:
@@ -150,12 +156,12 @@ class Plan:
     """A plan for `batch` same-shape instances, bound to a torch CUDA stream."""
 
     def __init__(self, nx, ny, nz, lx=2 * np.pi, ly=2.0, lz=2 * np.pi, precision=PPE_PREC_FP64, tol=1e-12,
-                 max_refine=1, batch=1, stream=None, device=None, ybc=PPE_YBC_WALLS):
+                 max_refine=1, batch=1, stream=None, device=None, ybc=PPE_YBC_WALLS, flags=0):
         import torch
 
         self._torch = torch
         self.lib = load()
-        self.desc = make_desc(nx, ny, nz, lx, ly, lz, precision, tol, max_refine, batch, ybc)
+        self.desc = make_desc(nx, ny, nz, lx, ly, lz, precision, tol, max_refine, batch, ybc, flags)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._h = ctypes.c_void_p()
@@ -240,6 +246,29 @@ class Plan:
                                 ctypes.c_void_p(info.data_ptr()))
         _check(st, "ppe_solve")
         return info
+
+    def solve_varcoef(self, rho0: Sequence[float], dt: Sequence[float], us, vs, ws, rho, pn, pnm1, S, p,
+                      max_iters: int, tol: float, info=None, hist=None):
+        """ppe_solve_varcoef: pressure of Eq. (25) by the split fixed point.
+        Returns (info, hist); hist is a float64 tensor [batch][max_iters + 1]
+        of relative residuals (-1 after convergence) when requested with
+        hist=True or given as a tensor."""
+        torch = self._torch
+        if info is None:
+            info = self.new_info()
+        if hist is True:
+            hist = torch.empty(self.batch * (max_iters + 1), dtype=torch.float64, device=self.device)
+        B = self.batch
+        if len(rho0) != B or len(dt) != B:
+            raise PPEError("rho0 and dt need one value per instance")
+        args = [self._batch(us, "us"), self._batch(vs, "vs", v=True), self._batch(ws, "ws"),
+                self._batch(rho, "rho"), self._batch(pn, "pn"), self._batch(pnm1, "pnm1"), self._batch(S, "S"),
+                self._batch(p, "p")]
+        hp = ctypes.c_void_p(hist.data_ptr()) if hist is not None else None
+        st = self.lib.ppe_solve_varcoef(self._h, _dbl(rho0), _dbl(dt), *[_ptrs(a) for a in args],
+                                        ctypes.c_void_p(info.data_ptr()), int(max_iters), float(tol), hp)
+        _check(st, "ppe_solve_varcoef")
+        return info, hist
 
     def correct(self, dt: Sequence[float], us, vs, ws, rho, pn, pnm1, p, S, u, v, w, info):
         """ppe_correct: writes u, v, w and the continuity fields of `info`."""

@@ -113,6 +113,7 @@ bool desc_ok(const ppe_desc_t* d) {
   if (!(d->lx > 0) || !(d->ly > 0) || !(d->lz > 0)) return false;
   if (d->precision != PPE_PREC_FP64 && d->precision != PPE_PREC_MIXED) return false;
   if (d->ybc != PPE_YBC_WALLS && d->ybc != PPE_YBC_OUTFLOW) return false;
+  if ((d->flags & ~PPE_FLAG_VARCOEF) != 0 || d->reserved != 0) return false;
   if (d->batch < 1 || d->batch > PPE_MAX_BATCH) return false;
   if (d->max_refine < 0 || d->max_refine > 64) return false;
   if (!(d->tol >= 0)) return false;
@@ -231,13 +232,16 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   return true;
 }
 
+// FP64 residual buffer: refinement sweeps and the split fixed-point iteration
+bool needs_r64(const ppe_desc_t& d) { return d.precision == PPE_PREC_MIXED || (d.flags & PPE_FLAG_VARCOEF) != 0; }
+
 size_t workspace_bytes(const ppe_plan_s* p) {
   const ppe_desc_t& d = p->d;
   const size_t B = (size_t)d.batch;
   size_t s = 0;
   s += B * (size_t)p->g.spec_elems * spec_elem_bytes(&d);
   s += B * (size_t)p->g.npts * 8;                                       // b64
-  if (d.precision == PPE_PREC_MIXED) s += B * (size_t)p->g.npts * 8;    // r64
+  if (needs_r64(d)) s += B * (size_t)p->g.npts * 8;                     // r64
   s += B * (size_t)d.ny * d.nz * 8;   // rowsum
   s += B * (size_t)d.ny * 8;          // colsum
   s += B * (size_t)kNScal * 8;        // scalars
@@ -360,10 +364,10 @@ void prof_collect(ppe_plan_s* p) {
   } while (0)
 
 void finish(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb, int nblk, int kind, int check,
-            double tol = 0.0, double* out = nullptr) {
+            double tol = 0.0, double* out = nullptr, int ostride = 0) {
   PPE_TIMED(p, "k_finish",
             (k_finish<<<nb, kFinishThreads, 0, p->stream>>>(tab, p->g, p->scal, p->partial, p->pstride, nblk, inst0, kind, check,
-                                                  tol, out)));
+                                                  tol, out, ostride)));
 }
 
 template <typename TS>
@@ -400,27 +404,32 @@ ppe_status_t launch_chain(ppe_plan_s* p, const Work<TS>& W, int nb, int check) {
   return launch_fft_z<TS>(p, W, nb, +1, check);
 }
 
+// rho0 = min(rho) on the device for the instances that ask for it (Eq. 27)
+void rho_min_pass(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) {
+  const Geom& g = p->g;
+  bool need_min = false;
+  for (int i = 0; i < nb; ++i) need_min |= !(tab.in[i].rho0_in > 0.0);
+  if (!need_min) return;
+  PPE_TIMED(p, "k_rho_min_init", (k_rho_min_init<<<1, 64, 0, p->stream>>>(p->scal, inst0, nb)));
+  const long long blocks = std::min<long long>((g.npts + 255) / 256, 1024);
+  PPE_TIMED(p, "k_rho_min", (k_rho_min<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->scal, inst0)));
+  PPE_TIMED(p, "k_rho_min_finish", (k_rho_min_finish<<<1, 64, 0, p->stream>>>(tab, p->scal, inst0, nb)));
+}
+
 template <typename TS>
 ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) {
   const Geom& g = p->g;
   Work<TS> W = make_work<TS>(p, inst0);
   const bool mixed = p->d.precision == PPE_PREC_MIXED;
   const double tol = mixed ? p->d.tol : 0.0;
-  bool need_min = false;
-  for (int i = 0; i < nb; ++i) need_min |= !(tab.in[i].rho0_in > 0.0);
-  if (need_min) {
-    PPE_TIMED(p, "k_rho_min_init", (k_rho_min_init<<<1, 64, 0, p->stream>>>(p->scal, inst0, nb)));
-    const long long blocks = std::min<long long>((g.npts + 255) / 256, 1024);
-    PPE_TIMED(p, "k_rho_min", (k_rho_min<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(tab, g, p->scal, inst0)));
-    PPE_TIMED(p, "k_rho_min_finish", (k_rho_min_finish<<<1, 64, 0, p->stream>>>(tab, p->scal, inst0, nb)));
-  }
+  rho_min_pass(p, tab, inst0, nb);
   const long long nrows = (long long)g.ny * g.nz;
   const long long npairs = (nrows + 1) / 2;
   dim3 xgrid((unsigned)((npairs + p->rp - 1) / p->rp), 1, nb);
   dim3 xblock(p->rp * p->fx.tc);
   FftDev fx = to_dev(p->fx);
   PPE_TIMED(p, "k_rhs",
-            PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads, march_lds(p->mrhs, 2),
+            PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT, true><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads, march_lds(p->mrhs, 2),
                                                         p->stream>>>(tab, g, p->mrhs.m, W))));
   // the right-hand-side sums are reduced by block 0 of the first row FFT
   PPE_TIMED(p, "k_r2c",
@@ -445,6 +454,57 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
       PPE_TIMED(p, "k_c2r",
                 PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1))));
     }
+  }
+  return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
+}
+
+// Split fixed-point iteration (Sec. 5.4): p_0 = 2 p^n - p^{n-1},
+// p_{k+1} = p_k + L^+ [c - rho0 D((1/rho_f) G p_k)], c = (rho0/dt)(D u* - S).
+// p_1 is the split solve; the fixed point is the pressure of Eq. (25).
+// Residual k is recorded in hist[inst][k] (k = 0 .. max_iters).
+template <typename TS>
+ppe_status_t varcoef_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb, int max_iters, double tol,
+                           double* hist) {
+  const Geom& g = p->g;
+  Work<TS> W = make_work<TS>(p, inst0);
+  rho_min_pass(p, tab, inst0, nb);
+  const long long nrows = (long long)g.ny * g.nz;
+  const long long npairs = (nrows + 1) / 2;
+  dim3 xgrid((unsigned)((npairs + p->rp - 1) / p->rp), 1, nb);
+  dim3 xblock(p->rp * p->fx.tc);
+  FftDev fx = to_dev(p->fx);
+  PPE_TIMED(p, "k_rhs",
+            PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT, false><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads,
+                                                               march_lds(p->mrhs, 1), p->stream>>>(tab, g,
+                                                                                                   p->mrhs.m, W))));
+  finish(p, tab, inst0, nb, p->mrhs.grid, FIN_RHS, 0, tol);
+  const int hs = max_iters + 1;
+  double* h0 = hist ? hist + (size_t)inst0 * hs : nullptr;
+  if (h0) {
+    const long long n = (long long)nb * hs;
+    PPE_TIMED(p, "k_fill", (k_fill<<<(unsigned)((n + 255) / 256), 256, 0, p->stream>>>(h0, n, -1.0)));
+  }
+  for (int it = 0; it <= max_iters; ++it) {
+    if (it == 0)
+      PPE_TIMED(p, "k_resid_var",
+                PPE_PPT_SWITCH(p->mres.ppt, (k_resid_var<TS, PPT, true><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
+                                                                         march_lds(p->mres, 2), p->stream>>>(
+                                                tab, g, p->mres.m, W, p->r64))));
+    else
+      PPE_TIMED(p, "k_resid_var",
+                PPE_PPT_SWITCH(p->mres.ppt, (k_resid_var<TS, PPT, false><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
+                                                                          march_lds(p->mres, 2), p->stream>>>(
+                                                tab, g, p->mres.m, W, p->r64))));
+    finish(p, tab, inst0, nb, p->mres.grid, it == max_iters ? FIN_RESID_LAST : FIN_RESID, 1, 0.0,
+           h0 ? h0 + it : nullptr, hs);
+    if (it == max_iters) break;
+    PPE_TIMED(p, "k_r2c",
+              PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
+                                     tab, g, fx, W, p->r64, p->rp, 1, FinishArgs{0, 0.0}))));
+    ppe_status_t st = launch_chain<TS>(p, W, nb, 1);
+    if (st != PPE_OK) return st;
+    PPE_TIMED(p, "k_c2r",
+              PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1))));
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
 }
@@ -528,7 +588,7 @@ ppe_status_t ppe_plan(const ppe_desc_t* desc, void* stream, ppe_plan_t* out) {
   bool ok = true;
   ok &= dalloc(p, (char**)&p->spec, B * (size_t)p->g.spec_elems * spec_elem_bytes(&d)) == hipSuccess;
   ok &= dalloc(p, &p->b64, B * (size_t)p->g.npts * 8) == hipSuccess;
-  if (d.precision == PPE_PREC_MIXED) ok &= dalloc(p, &p->r64, B * (size_t)p->g.npts * 8) == hipSuccess;
+  if (needs_r64(d)) ok &= dalloc(p, &p->r64, B * (size_t)p->g.npts * 8) == hipSuccess;
   ok &= dalloc(p, &p->rowsum, B * (size_t)d.ny * d.nz * 8) == hipSuccess;
   ok &= dalloc(p, &p->colsum, B * (size_t)d.ny * 8) == hipSuccess;
   ok &= dalloc(p, &p->scal, B * kNScal * 8) == hipSuccess;
@@ -614,6 +674,51 @@ ppe_status_t ppe_solve(ppe_plan_t p, const double* rho0, const double* dt, const
     }
     ppe_status_t st = (p->d.precision == PPE_PREC_FP64) ? solve_typed<double>(p, tab, i0, nb)
                                                          : solve_typed<float>(p, tab, i0, nb);
+    if (st != PPE_OK) return st;
+  }
+  return PPE_OK;
+}
+
+ppe_status_t ppe_solve_varcoef(ppe_plan_t p, const double* rho0, const double* dt, const double* const* us,
+                               const double* const* vs, const double* const* ws, const double* const* rho,
+                               const double* const* pn, const double* const* pnm1, const double* const* S,
+                               double* const* pout, ppe_info_t* info, int32_t max_iters, double tol,
+                               double* hist) {
+  if (!p || !rho0 || !dt || !info) return PPE_ERR_ARG;
+  if (!p->r64) return PPE_ERR_ARG;  // plan built without the residual buffer
+  if (max_iters < 0 || max_iters > 100000 || !(tol >= 0)) return PPE_ERR_ARG;
+  const int B = p->d.batch;
+  if (!ptrs_ok((const void* const*)us, B) || !ptrs_ok((const void* const*)vs, B) ||
+      !ptrs_ok((const void* const*)ws, B) || !ptrs_ok((const void* const*)rho, B) ||
+      !ptrs_ok((const void* const*)pn, B) || !ptrs_ok((const void* const*)pnm1, B) ||
+      !ptrs_ok((const void* const*)S, B) || !ptrs_ok((const void* const*)pout, B))
+    return PPE_ERR_ARG;
+  for (int i = 0; i < B; ++i) {
+    if (!(dt[i] > 0) || !std::isfinite(dt[i]) || std::isnan(rho0[i])) return PPE_ERR_ARG;
+    if (pout[i] == pn[i] || pout[i] == pnm1[i]) return PPE_ERR_ARG;
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
+  for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
+    const int nb = std::min(kMaxLaunch, B - i0);
+    PtrTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    for (int i = 0; i < nb; ++i) {
+      InstPtrs& q = tab.in[i];
+      q.us = us[i0 + i];
+      q.vs = vs[i0 + i];
+      q.ws = ws[i0 + i];
+      q.rho = rho[i0 + i];
+      q.pn = pn[i0 + i];
+      q.pnm1 = pnm1[i0 + i];
+      q.S = S[i0 + i];
+      q.p = pout[i0 + i];
+      q.info = info + i0 + i;
+      q.rho0_in = rho0[i0 + i];
+      q.dt = dt[i0 + i];
+    }
+    ppe_status_t st = (p->d.precision == PPE_PREC_FP64)
+                          ? varcoef_typed<double>(p, tab, i0, nb, max_iters, tol, hist)
+                          : varcoef_typed<float>(p, tab, i0, nb, max_iters, tol, hist);
     if (st != PPE_OK) return st;
   }
   return PPE_OK;

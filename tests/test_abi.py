@@ -45,7 +45,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_struct_layouts():
-    assert ctypes.sizeof(binding.Desc) == 64
+    assert ctypes.sizeof(binding.Desc) == 72
     assert binding.INFO_DTYPE.itemsize == 64
 
 
