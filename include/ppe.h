@@ -175,9 +175,10 @@ ppe_status_t ppe_solve(ppe_plan_t plan, const double* rho0, const double* dt,
  * reaches tol, or after max_iters updates (>= 0; 0 only evaluates res_0).
  * The plan needs PPE_FLAG_VARCOEF or PPE_PREC_MIXED (else PPE_ERR_ARG).
  *   p     : output, must not alias p^n or p^{n-1}
- *   info  : status (PPE_ERR_NOT_CONVERGED if res > tol after max_iters, or
- *           NONFINITE), iters = updates applied, res_rel = last residual,
- *           rho0_used, compat_defect
+ *   tol   : 0 runs max_iters sweeps without a convergence test
+ *   info  : status (PPE_ERR_NOT_CONVERGED if tol > 0 and res > tol after
+ *           max_iters, or NONFINITE), iters = updates applied, res_rel = last
+ *           residual, rho0_used, compat_defect
  *   hist  : NULL or a device array [batch][max_iters + 1]; hist[b][k] = res_k,
  *           -1 after convergence
  * ppe_correct(pn = p, pnm1 = p, p) then applies the variable-density
@@ -188,6 +189,48 @@ ppe_status_t ppe_solve_varcoef(ppe_plan_t plan, const double* rho0, const double
                                const double* const* rho, const double* const* pn, const double* const* pnm1,
                                const double* const* S, double* const* p, ppe_info_t* info,
                                int32_t max_iters, double tol, double* hist);
+
+/* Pressure history resident in device memory, for time loops.  A ring holds
+ * three pressure buffers per instance (p^{n-1}, p^n and the next pressure);
+ * each step solves with p_hat = 2 p^n - p^{n-1} taken from the ring (Eq. 27),
+ * writes p^{n+1} into the oldest buffer, applies the projection (Eq. 28) and
+ * rotates, so a time loop moves no pressure data between steps.  The ring
+ * owns its buffers (3 * batch * nx*ny*nz doubles) and uses the plan's stream;
+ * the plan must outlive the ring. */
+typedef struct ppe_ring_s* ppe_ring_t;
+
+/* pn, pnm1: host arrays of `batch` device pointers, copied into the ring
+ * (stream-ordered).  pnm1 may be NULL: p^{n-1} = p^n, so the first p_hat is p^n. */
+ppe_status_t ppe_ring_create(ppe_plan_t plan, const double* const* pn, const double* const* pnm1, ppe_ring_t* out);
+
+/* One projection step: ppe_solve + ppe_correct with the ring's history, then
+ * rotate (the new pressure becomes p^n).  Arguments as for those calls.
+ * split_defect: NULL, or a device array [batch][2] that receives the relative
+ * residual of the variable-coefficient problem, Eq. (25), for p_hat ([b][0])
+ * and for the split pressure p^{n+1} ([b][1]) -- how far the split is from
+ * the variable-density projection this step (Sec. 5.4).  It needs the plan's
+ * residual buffer (PPE_FLAG_VARCOEF or PPE_PREC_MIXED) and takes the
+ * pressure from one sweep of ppe_solve_varcoef (equal to ppe_solve's to
+ * rounding). */
+ppe_status_t ppe_ring_step(ppe_ring_t ring, const double* rho0, const double* dt,
+                           const double* const* us, const double* const* vs, const double* const* ws,
+                           const double* const* rho, const double* const* S,
+                           double* const* u, double* const* v, double* const* w, ppe_info_t* info,
+                           double* split_defect);
+
+/* Device pointers of the ring's pressures: lag 0 = p^n (the newest), lag 1 =
+ * p^{n-1}.  p: host array of `batch` entries. */
+ppe_status_t ppe_ring_pressure(ppe_ring_t ring, int32_t lag, double** p);
+
+/* Copy the ring's pressure of the given lag into caller buffers (host array
+ * of `batch` device pointers), stream-ordered on the plan's stream. */
+ppe_status_t ppe_ring_read(ppe_ring_t ring, int32_t lag, double* const* out);
+
+/* Steps taken since creation. */
+int64_t ppe_ring_steps(ppe_ring_t ring);
+
+/* Free the ring's buffers (waits for the plan's stream first). */
+ppe_status_t ppe_ring_destroy(ppe_ring_t ring);
 
 /* Projection, Eq. (28) (Sec. 5.4), and the continuity check of the result.
  * Reads rho0_used and compat_defect from `info` (as written by ppe_solve for

@@ -52,7 +52,8 @@ INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("rho0_used", "<f8")
 assert INFO_DTYPE.itemsize == 64
 
 EXPORTS = ["ppe_plan_workspace_bytes", "ppe_plan", "ppe_plan_destroy", "ppe_plan_set_stream", "ppe_solve",
-           "ppe_correct", "ppe_residual", "ppe_source", "ppe_solve_varcoef", "ppe_plan_profile",
+           "ppe_correct", "ppe_residual", "ppe_source", "ppe_solve_varcoef", "ppe_ring_create", "ppe_ring_step",
+           "ppe_ring_pressure", "ppe_ring_read", "ppe_ring_steps", "ppe_ring_destroy", "ppe_plan_profile",
            "ppe_plan_profile_read", "ppe_version"]
 
 SOURCE_FIELDS = ("C", "div_g", "div_l", "mdot", "area", "rho_g", "rho_l")
@@ -105,6 +106,18 @@ def load(path: str = LIB_PATH):
     lib.ppe_solve_varcoef.argtypes = [P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, P, ctypes.c_int32, ctypes.c_double,
                                       P]
     lib.ppe_solve_varcoef.restype = ctypes.c_int
+    lib.ppe_ring_create.argtypes = [P, PP, PP, ctypes.POINTER(P)]
+    lib.ppe_ring_create.restype = ctypes.c_int
+    lib.ppe_ring_step.argtypes = [P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, P, P]
+    lib.ppe_ring_step.restype = ctypes.c_int
+    lib.ppe_ring_pressure.argtypes = [P, ctypes.c_int32, PP]
+    lib.ppe_ring_pressure.restype = ctypes.c_int
+    lib.ppe_ring_read.argtypes = [P, ctypes.c_int32, PP]
+    lib.ppe_ring_read.restype = ctypes.c_int
+    lib.ppe_ring_steps.argtypes = [P]
+    lib.ppe_ring_steps.restype = ctypes.c_int64
+    lib.ppe_ring_destroy.argtypes = [P]
+    lib.ppe_ring_destroy.restype = ctypes.c_int
     lib.ppe_plan_profile.argtypes = [P, ctypes.c_int32]
     lib.ppe_plan_profile.restype = ctypes.c_int
     lib.ppe_plan_profile_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_int32,
@@ -320,6 +333,62 @@ def to_device(problem, device="cuda"):
 
     return {k: torch.from_numpy(np.ascontiguousarray(getattr(problem, k))).to(device)
             for k in ("us", "vs", "ws", "rho", "pn", "pnm1", "S")}
+
+
+class Ring:
+    """Device-resident pressure history for a time loop (ppe_ring_*)."""
+
+    def __init__(self, plan: Plan, pn, pnm1=None):
+        self.plan = plan
+        self.lib = plan.lib
+        self._h = ctypes.c_void_p()
+        a = _ptrs(plan._batch(pn, "pn"))
+        b = _ptrs(plan._batch(pnm1, "pnm1")) if pnm1 is not None else None
+        _check(self.lib.ppe_ring_create(plan._h, a, b, ctypes.byref(self._h)), "ppe_ring_create")
+
+    def step(self, rho0, dt, us, vs, ws, rho, S, u, v, w, info=None, defect=False):
+        """One projection step with the ring's history; returns (info, defect)
+        where defect is a [batch][2] tensor of Eq. (25) residuals when asked."""
+        plan = self.plan
+        torch = plan._torch
+        if info is None:
+            info = plan.new_info()
+        d = None
+        if defect is True:
+            d = torch.empty(plan.batch * 2, dtype=torch.float64, device=plan.device)
+        elif defect is not False and defect is not None:
+            d = defect
+        B = plan.batch
+        if len(rho0) != B or len(dt) != B:
+            raise PPEError("rho0 and dt need one value per instance")
+        args = [plan._batch(us, "us"), plan._batch(vs, "vs", v=True), plan._batch(ws, "ws"),
+                plan._batch(rho, "rho"), plan._batch(S, "S"), plan._batch(u, "u"), plan._batch(v, "v", v=True),
+                plan._batch(w, "w")]
+        st = self.lib.ppe_ring_step(self._h, _dbl(rho0), _dbl(dt), *[_ptrs(x) for x in args],
+                                    ctypes.c_void_p(info.data_ptr()),
+                                    ctypes.c_void_p(d.data_ptr()) if d is not None else None)
+        _check(st, "ppe_ring_step")
+        return info, d
+
+    def read(self, lag, out):
+        """Copy p^n (lag 0) or p^{n-1} (lag 1) into the tensors `out`."""
+        _check(self.lib.ppe_ring_read(self._h, int(lag), _ptrs(self.plan._batch(out, "out"))), "ppe_ring_read")
+        return out
+
+    @property
+    def steps(self) -> int:
+        return int(self.lib.ppe_ring_steps(self._h))
+
+    def close(self):
+        if self._h:
+            self.lib.ppe_ring_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sources_to_device(src, device="cuda") -> Dict:

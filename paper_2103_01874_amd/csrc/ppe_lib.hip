@@ -855,6 +855,113 @@ ppe_status_t ppe_source(ppe_plan_t p, const ppe_source_t* src, double* const* S)
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
 }
 
+// ---------------------------------------------------------------------------
+// Pressure ring for time loops
+// ---------------------------------------------------------------------------
+struct ppe_ring_s {
+  ppe_plan_t plan = nullptr;
+  double* buf[3] = {nullptr, nullptr, nullptr};  // each batch * npts doubles
+  int cur = 0, prev = 1;                          // slots of p^n and p^{n-1}
+  int64_t steps = 0;
+};
+
+ppe_status_t ppe_ring_create(ppe_plan_t p, const double* const* pn, const double* const* pnm1, ppe_ring_t* out) {
+  if (!out) return PPE_ERR_ARG;
+  *out = nullptr;
+  if (!p || !ptrs_ok((const void* const*)pn, p->d.batch)) return PPE_ERR_ARG;
+  if (pnm1 && !ptrs_ok((const void* const*)pnm1, p->d.batch)) return PPE_ERR_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
+  ppe_ring_s* r = new (std::nothrow) ppe_ring_s();
+  if (!r) return PPE_ERR_NOMEM;
+  r->plan = p;
+  const size_t n = (size_t)p->g.npts;
+  const size_t bytes = (size_t)p->d.batch * n * sizeof(double);
+  for (int s = 0; s < 3; ++s) {
+    if (hipMalloc((void**)&r->buf[s], bytes) != hipSuccess) {
+      for (int q = 0; q < s; ++q) (void)hipFree(r->buf[q]);
+      delete r;
+      return PPE_ERR_NOMEM;
+    }
+  }
+  bool ok = true;
+  for (int i = 0; i < p->d.batch; ++i) {
+    ok &= hipMemcpyAsync(r->buf[r->cur] + i * n, pn[i], n * sizeof(double), hipMemcpyDeviceToDevice, p->stream) ==
+          hipSuccess;
+    ok &= hipMemcpyAsync(r->buf[r->prev] + i * n, pnm1 ? pnm1[i] : pn[i], n * sizeof(double),
+                         hipMemcpyDeviceToDevice, p->stream) == hipSuccess;
+  }
+  if (!ok) {
+    (void)hipStreamSynchronize(p->stream);
+    for (int s = 0; s < 3; ++s) (void)hipFree(r->buf[s]);
+    delete r;
+    return PPE_ERR_DEVICE;
+  }
+  *out = r;
+  return PPE_OK;
+}
+
+ppe_status_t ppe_ring_step(ppe_ring_t r, const double* rho0, const double* dt, const double* const* us,
+                           const double* const* vs, const double* const* ws, const double* const* rho,
+                           const double* const* S, double* const* u, double* const* v, double* const* w,
+                           ppe_info_t* info, double* split_defect) {
+  if (!r) return PPE_ERR_ARG;
+  ppe_plan_t p = r->plan;
+  const int B = p->d.batch;
+  if (B > PPE_MAX_BATCH) return PPE_ERR_ARG;
+  const int next = 3 - r->cur - r->prev;
+  const size_t n = (size_t)p->g.npts;
+  const double* pn[PPE_MAX_BATCH];
+  const double* pm[PPE_MAX_BATCH];
+  double* pp[PPE_MAX_BATCH];
+  for (int i = 0; i < B; ++i) {
+    pn[i] = r->buf[r->cur] + i * n;
+    pm[i] = r->buf[r->prev] + i * n;
+    pp[i] = r->buf[next] + i * n;
+  }
+  ppe_status_t st = split_defect ? ppe_solve_varcoef(p, rho0, dt, us, vs, ws, rho, pn, pm, S, pp, info, 1, 0.0,
+                                                     split_defect)
+                                 : ppe_solve(p, rho0, dt, us, vs, ws, rho, pn, pm, S, pp, info);
+  if (st != PPE_OK) return st;
+  st = ppe_correct(p, dt, us, vs, ws, rho, pn, pm, pp, S, u, v, w, info);
+  if (st != PPE_OK) return st;
+  r->prev = r->cur;
+  r->cur = next;
+  ++r->steps;
+  return PPE_OK;
+}
+
+ppe_status_t ppe_ring_pressure(ppe_ring_t r, int32_t lag, double** out) {
+  if (!r || !out || (lag != 0 && lag != 1)) return PPE_ERR_ARG;
+  const size_t n = (size_t)r->plan->g.npts;
+  const int s = lag == 0 ? r->cur : r->prev;
+  for (int i = 0; i < r->plan->d.batch; ++i) out[i] = r->buf[s] + i * n;
+  return PPE_OK;
+}
+
+ppe_status_t ppe_ring_read(ppe_ring_t r, int32_t lag, double* const* out) {
+  if (!r || (lag != 0 && lag != 1) || !ptrs_ok((const void* const*)out, r->plan->d.batch)) return PPE_ERR_ARG;
+  ppe_plan_t p = r->plan;
+  if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
+  const size_t n = (size_t)p->g.npts;
+  const int s = lag == 0 ? r->cur : r->prev;
+  for (int i = 0; i < p->d.batch; ++i)
+    if (hipMemcpyAsync(out[i], r->buf[s] + i * n, n * sizeof(double), hipMemcpyDeviceToDevice, p->stream) !=
+        hipSuccess)
+      return PPE_ERR_DEVICE;
+  return PPE_OK;
+}
+
+int64_t ppe_ring_steps(ppe_ring_t r) { return r ? r->steps : -1; }
+
+ppe_status_t ppe_ring_destroy(ppe_ring_t r) {
+  if (!r) return PPE_ERR_ARG;
+  (void)hipSetDevice(r->plan->device);
+  (void)hipStreamSynchronize(r->plan->stream);
+  for (int s = 0; s < 3; ++s) (void)hipFree(r->buf[s]);
+  delete r;
+  return PPE_OK;
+}
+
 ppe_status_t ppe_plan_profile(ppe_plan_t p, int32_t enable) {
   if (!p) return PPE_ERR_ARG;
   if (enable) {
