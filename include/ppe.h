@@ -181,6 +181,11 @@ ppe_status_t ppe_solve(ppe_plan_t plan, const double* rho0, const double* dt,
  *           residual, rho0_used, compat_defect
  *   hist  : NULL or a device array [batch][max_iters + 1]; hist[b][k] = res_k,
  *           -1 after convergence
+ * With tol > 0 the host stops enqueuing sweeps once every instance has
+ * converged: every 4 sweeps the convergence flags are copied to pinned host
+ * memory, and before enqueuing further sweeps the call waits for the copy
+ * made 4 sweeps earlier (so it blocks the host while at most 4 more sweeps
+ * are queued).  With tol = 0 it only enqueues, like ppe_solve.
  * ppe_correct(pn = p, pnm1 = p, p) then applies the variable-density
  * projection u^{n+1} = u* - dt G p / rho_f, whose relative divergence error
  * is the last res. */

@@ -73,7 +73,11 @@ struct ppe_plan_s {
     int ppt = 1;     // interior points per thread per plane (kernel template)
     int tslots = 0;  // LDS slots of a tile plane with its halo ring
   } mrhs, mcor, mres;
-  double* r64 = nullptr;   // refinement residual (mixed only)
+  double* r64 = nullptr;   // refinement / fixed-point residual (mixed, or PPE_FLAG_VARCOEF)
+  // fixed-point iteration: convergence flags copied to pinned host memory
+  // every few sweeps, so the host stops enqueuing once all instances converged
+  double* conv_host = nullptr;      // [2][kMaxLaunch * kNScal], hipHostMalloc
+  hipEvent_t conv_ev[2] = {nullptr, nullptr};
   long long pstride = 0;
   // device memory
   void* spec = nullptr;
@@ -266,6 +270,9 @@ void free_plan(ppe_plan_s* p) {
     (void)hipEventDestroy(e.b);
   }
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->conv_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (p->conv_host) (void)hipHostFree(p->conv_host);
   void* ptrs[] = {p->spec, p->b64, p->r64, p->rowsum, p->colsum, p->scal, p->partial,
                   p->lamx, p->lamz, p->fx.tw, p->fz.tw};
   for (void* q : ptrs)
@@ -484,7 +491,27 @@ ppe_status_t varcoef_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb
     const long long n = (long long)nb * hs;
     PPE_TIMED(p, "k_fill", (k_fill<<<(unsigned)((n + 255) / 256), 256, 0, p->stream>>>(h0, n, -1.0)));
   }
+  // every kPoll sweeps the instances' scalars go to pinned host memory behind
+  // an event; before enqueuing more, the host reads the previous chunk's copy
+  // (one chunk of run-ahead keeps the device busy) and stops once every
+  // instance has converged
+  constexpr int kPoll = 4;
   for (int it = 0; it <= max_iters; ++it) {
+    if (it > 0 && it % kPoll == 0 && tol > 0.0) {
+      const int c = it / kPoll;
+      double* h = p->conv_host + (size_t)(c & 1) * kMaxLaunch * kNScal;
+      if (hipMemcpyAsync(h, p->scal + (size_t)inst0 * kNScal, (size_t)nb * kNScal * sizeof(double),
+                         hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+          hipEventRecord(p->conv_ev[c & 1], p->stream) != hipSuccess)
+        return PPE_ERR_DEVICE;
+      if (c >= 2) {
+        if (hipEventSynchronize(p->conv_ev[(c - 1) & 1]) != hipSuccess) return PPE_ERR_DEVICE;
+        const double* hp = p->conv_host + (size_t)((c - 1) & 1) * kMaxLaunch * kNScal;
+        bool all = true;
+        for (int i = 0; i < nb; ++i) all = all && hp[(size_t)i * kNScal + SC_CONV] != 0.0;
+        if (all) break;
+      }
+    }
     if (it == 0)
       PPE_TIMED(p, "k_resid_var",
                 PPE_PPT_SWITCH(p->mres.ppt, (k_resid_var<TS, PPT, true><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
@@ -588,7 +615,12 @@ ppe_status_t ppe_plan(const ppe_desc_t* desc, void* stream, ppe_plan_t* out) {
   bool ok = true;
   ok &= dalloc(p, (char**)&p->spec, B * (size_t)p->g.spec_elems * spec_elem_bytes(&d)) == hipSuccess;
   ok &= dalloc(p, &p->b64, B * (size_t)p->g.npts * 8) == hipSuccess;
-  if (needs_r64(d)) ok &= dalloc(p, &p->r64, B * (size_t)p->g.npts * 8) == hipSuccess;
+  if (needs_r64(d)) {
+    ok &= dalloc(p, &p->r64, B * (size_t)p->g.npts * 8) == hipSuccess;
+    ok &= hipHostMalloc((void**)&p->conv_host, 2 * kMaxLaunch * kNScal * sizeof(double), hipHostMallocDefault) ==
+          hipSuccess;
+    for (hipEvent_t& e : p->conv_ev) ok &= hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  }
   ok &= dalloc(p, &p->rowsum, B * (size_t)d.ny * d.nz * 8) == hipSuccess;
   ok &= dalloc(p, &p->colsum, B * (size_t)d.ny * 8) == hipSuccess;
   ok &= dalloc(p, &p->scal, B * kNScal * 8) == hipSuccess;
