@@ -159,15 +159,24 @@ PPE_HD void dft(cplx<T>* v) {
 }
 
 // LDS slot of element n of a transform.  Rows (es == 1) are padded with one
-// slot per 8 elements: the first Stockham stages write with a stride of R
-// elements, which without padding puts every lane of a wavefront on the same
-// LDS banks.  Columns (es > 1, several transforms side by side) are unpadded.
+// slot per 2^kRowPadShift elements: the first Stockham stages write with a
+// stride of R elements, which without padding puts every lane of a wavefront
+// on the same LDS banks.  Columns (es > 1, several transforms side by side)
+// sit at stride es; the z kernel adds kColPad slots to its column count.
+#ifndef PPE_ROW_PAD_SHIFT
+#define PPE_ROW_PAD_SHIFT 3
+#endif
+#ifndef PPE_COL_PAD
+#define PPE_COL_PAD 0
+#endif
+constexpr int kRowPadShift = PPE_ROW_PAD_SHIFT;
+constexpr int kColPad = PPE_COL_PAD;
 template <bool PAD>
 PPE_HD int lslot(int n, int es) {
-  return PAD ? n + (n >> 3) : n * es;
+  return PAD ? n + (n >> kRowPadShift) : n * es;
 }
 // Slots a padded row of n elements occupies.
-PPE_HD int padded_len(int n) { return n + (n >> 3) + 1; }
+PPE_HD int padded_len(int n) { return n + (n >> kRowPadShift) + 1; }
 
 // One Stockham stage, split into its read and write halves.
 //   element n of the transform lives at buf[lslot(n, es)]

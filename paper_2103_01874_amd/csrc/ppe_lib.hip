@@ -197,12 +197,14 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   // z FFT: TX columns of tc threads
   const int tcz = p->fz.tc;
   if (tcz > 512) return false;
-  // one 128-byte kx tile per block when LDS allows (TX must divide the tile)
-  p->tx = 1 << g.tws;
+  // 8 kx columns per block when LDS allows (TX divides the tile: all of an
+  // FP64 tile, half of an FP32 one, which measured faster than a full tile)
+  p->tx = std::min(1 << g.tws, 8);
   if (tune_env("PPE_TUNE_TX") > 0) p->tx = std::min(p->tx, tune_env("PPE_TUNE_TX"));
-  while (p->tx > 1 && ((size_t)d.nz * p->tx * 16 + (size_t)d.nz * 16 > lds_limit || p->tx * tcz > 512)) p->tx /= 2;
+  while (p->tx > 1 && ((size_t)d.nz * (p->tx + kColPad) * 16 + (size_t)d.nz * 16 > lds_limit || p->tx * tcz > 512))
+    p->tx /= 2;
   // columns + twiddle table (the plane-sum reduction reuses the column area)
-  p->lds_z = std::max((size_t)d.nz * p->tx * 16, (size_t)p->tx * tcz * 8) + (size_t)d.nz * 16;
+  p->lds_z = std::max((size_t)d.nz * (p->tx + kColPad) * 16, (size_t)p->tx * tcz * 8) + (size_t)d.nz * 16;
   // tri: P chunks of 2..16 rows, TXS systems per block
   const int chunk = tune_env("PPE_TUNE_CHUNK") > 0 ? tune_env("PPE_TUNE_CHUNK") : 8;
   int P = (int)std::lround(d.ny / (double)chunk);
@@ -549,11 +551,13 @@ namespace {
 // Dynamic LDS above 64 KiB must be enabled per kernel (all z-FFT variants).
 template <typename TS, int E>
 hipError_t allow_big_lds_e(int bytes) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_z<TS, E, -1>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_z<TS, E, +1>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* fns[] = {reinterpret_cast<const void*>(&k_fft_z<TS, E, -1>),
+                       reinterpret_cast<const void*>(&k_fft_z<TS, E, +1>)};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 template <typename TS>
 hipError_t allow_big_lds_t(int bytes) {
