@@ -83,6 +83,8 @@ __all__ = [
     "energy_norm",
     "split_map",
     "split_fixed_point",
+    "smart_face",
+    "predictor",
 ]
 
 
@@ -480,3 +482,251 @@ def split_fixed_point(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, S, iters, to
         k += 1
         res.append(residual(p))
     return {"p": p, "iters": k, "res": res, "upd_E": upd, "rho0": r0}
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5.4, Eq. (23): the predictor u^p (input of the projection)
+# ---------------------------------------------------------------------------
+#
+# Finite volumes on the staggered mesh (Sec. 5.4: SMART convection, second-
+# order central viscous term, CSF surface tension with density scaling):
+#   u^p = [ rho^n_f u^n + dt ( -div(rho u u)^n + div(tau)^n
+#                              + (rho^{n+1}_f/<rho>)(sigma_f kappa_f grad C + f_s) ) ] / rho^{n+1}_f
+# Readings (each listed in the design notes):
+#   * rho_f on a face: mean of its two cells (as in the projection); the mass
+#     flux through a momentum control-volume face is the mean of the two
+#     neighbouring face mass fluxes (rho_f times face velocity), or at a cell
+#     centre the cell density times the mean of the two face velocities;
+#   * the advected velocity on a control-volume face: SMART in normalised
+#     variables; where any cell touching that face is an interface cell
+#     (0 < C < 1), central differences if the cell Peclet number
+#     |m| h / mu < 2, else first-order upwind;
+#   * tau = mu [grad u + grad u^T - (2/3)(div u) I] (Sec. 2) with the velocity
+#     of the viscous term given separately (the paper's phase-wise velocities;
+#     defaults to u^n); mu at a cell centre, or the mean of the four cells
+#     around an edge;
+#   * sigma and kappa on a face by Eq. (30); grad C the face difference;
+#     f_s the tangential (Marangoni) force on faces, given;
+#   * y ends: ghost cells mirror the first two cells (cell fields and the
+#     tangential velocities u, w); v beyond a wall or symmetry face is the
+#     odd reflection 2 v_b - v, beyond an outflow face it equals v_ny; a
+#     ghost cell's stress comes from these ghost velocities; wall faces of v
+#     keep v^n, an outflow face is predicted.
+
+
+def smart_face(U, Cc, D):
+    """SMART value on a face from far-upwind U, upwind Cc and downwind D
+    (normalised variable phi_C = (Cc - U)/(D - U); bounded QUICK)."""
+    U, Cc, D = np.broadcast_arrays(np.asarray(U, float), np.asarray(Cc, float), np.asarray(D, float))
+    den = D - U
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ph = np.where(den != 0.0, (Cc - U) / np.where(den != 0.0, den, 1.0), -1.0)
+    pf = np.where((ph > 0) & (ph < 1.0 / 6.0), 3.0 * ph,
+         np.where((ph >= 1.0 / 6.0) & (ph < 5.0 / 6.0), 0.75 * ph + 0.375,
+         np.where((ph >= 5.0 / 6.0) & (ph < 1.0), 1.0, ph)))
+    out = U + pf * den
+    # outside 0 < phi_C < 1 (or flat data) the scheme is upwind
+    return np.where((ph > 0) & (ph < 1.0), out, Cc)
+
+
+def _advected(m, Um, Cm, Dm, Up, Cp, Dp, iface, mu_face, h):
+    """Face value for mass flux m: the m >= 0 stencil is (Um, Cm, Dm), the
+    m < 0 one (Up, Cp, Dp); the interface rule uses the cell Peclet number."""
+    pos = m >= 0
+    U = np.where(pos, Um, Up)
+    Cc = np.where(pos, Cm, Cp)
+    D = np.where(pos, Dm, Dp)
+    s = smart_face(U, Cc, D)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        pe = np.abs(m) * h / mu_face
+    hyb = np.where(pe < 2.0, 0.5 * (Cc + D), Cc)
+    return np.where(iface, hyb, s)
+
+
+def _yext(a, lo, hi):
+    """Two ghost layers on each side of axis 1 from callables lo(a), hi(a)."""
+    return np.concatenate([lo(a), a, hi(a)], axis=1)
+
+
+def _mirror(a):
+    return _yext(a, lambda x: x[:, 1::-1, :], lambda x: x[:, :-3:-1, :])
+
+
+def _faceavg(a, b):
+    """Eq. (30): one side's value where the other is zero, else the mean."""
+    return np.where(a == 0.0, b, np.where(b == 0.0, a, 0.5 * (a + b)))
+
+
+def predictor(g: Grid, dt, rho_mean, u, v, w, rho_n, rho_np1, mu, C, sigma, kappa,
+              uv=None, vv=None, wv=None, fsx=None, fsy=None, fsz=None):
+    """u^p, v^p, w^p of Eq. (23).  Needs ny >= 4."""
+    if g.ny < 4:
+        raise ValueError("the predictor needs ny >= 4")
+    f = lambda a: np.asarray(a, dtype=np.float64)
+    u, v, w, rho_n, rho_np1, mu, C, sigma, kappa = map(f, (u, v, w, rho_n, rho_np1, mu, C, sigma, kappa))
+    uv = u if uv is None else f(uv)
+    vv = v if vv is None else f(vv)
+    wv = w if wv is None else f(wv)
+    nz, ny, nx = g.shape
+    dx, dy, dz = g.dx, g.dy, g.dz
+    X, Z = 2, 0
+    sh = lambda a, s, ax: np.roll(a, s, axis=ax)   # sh(a, 1, X)[i] = a[i-1]
+
+    # y-extended arrays: index J + 2 holds row J
+    R = _mirror(rho_n)
+    Rn1 = _mirror(rho_np1)
+    M = _mirror(mu)
+    Ce = _mirror(C)
+    Ue, Uve = _mirror(u), _mirror(uv)
+    We, Wve = _mirror(w), _mirror(wv)
+
+    def vext(a):
+        lo = lambda x: 2.0 * x[:, :1, :] - x[:, 2:0:-1, :]
+        if g.ybc == 1:
+            hi = lambda x: np.repeat(x[:, -1:, :], 2, axis=1)
+        else:
+            hi = lambda x: 2.0 * x[:, -1:, :] - x[:, -2:-4:-1, :]
+        return _yext(a, lo, hi)
+    Ve, Vve = vext(v), vext(vv)        # face J at index J + 2, J = -2 .. ny + 2
+    # cell divergence of the viscous-term velocity on real and ghost rows,
+    # from the (ghost-extended) velocities: row J at index J + 2
+    Dv = ((sh(Uve, -1, X) - Uve) / dx + (Vve[:, 1:, :] - Vve[:, :-1, :])[:, :ny + 4, :] / dy
+          + (sh(Wve, -1, Z) - Wve) / dz)
+    iface = (Ce > 0.0) & (Ce < 1.0)
+    rows = slice(2, 2 + ny)            # the real cell rows in extended arrays
+
+
+    # face densities on u, w faces (real rows) and v faces (extended)
+    rxn, rxn1 = 0.5 * (R + sh(R, 1, X)), 0.5 * (Rn1 + sh(Rn1, 1, X))
+    rzn, rzn1 = 0.5 * (R + sh(R, 1, Z)), 0.5 * (Rn1 + sh(Rn1, 1, Z))
+    ryn = 0.5 * (R[:, 1:, :] + R[:, :-1, :])      # face J at index J + 1 (J = -1 .. ny + 2)
+    ryn1 = 0.5 * (Rn1[:, 1:, :] + Rn1[:, :-1, :])
+
+    def vface(a, J0, J1):
+        """Extended v-face array rows J0..J1-1 (J real face index)."""
+        return a[:, J0 + 2:J1 + 2, :]
+
+    def yface_rho(J0, J1, n1=False):
+        a = ryn1 if n1 else ryn
+        return a[:, J0 + 1:J1 + 1, :]
+
+    # ---------------- x momentum on u faces --------------------------------
+    # x: control-volume faces at cell centres i (between u_i and u_{i+1})
+    m = R * 0.5 * (Ue + sh(Ue, -1, X))
+    ut = _advected(m, sh(Ue, 1, X), Ue, sh(Ue, -1, X), sh(Ue, -2, X), sh(Ue, -1, X), Ue, iface, M, dx)
+    Fx = m * ut
+    conv = (Fx - sh(Fx, 1, X))[:, rows, :] / dx
+    # y: edges at v-face rows J = 0..ny, between u rows J-1 and J
+    J = np.arange(ny + 1)
+    rv = yface_rho(0, ny + 1) * vface(Ve, 0, ny + 1)      # (rho v) on v faces, column i
+    mE = 0.5 * (rv + sh(rv, 1, X))                          # columns i-1 and i
+    u_m2, u_m1, u_0, u_p1 = (Ue[:, J + 2 + o, :] for o in (-2, -1, 0, 1))
+    ie = iface[:, J + 1, :] | iface[:, J + 2, :]
+    ie = ie | sh(ie, 1, X)
+    me = 0.25 * (M[:, J + 1, :] + M[:, J + 2, :])
+    me = me + sh(me, 1, X)
+    ut = _advected(mE, u_m2, u_m1, u_0, u_p1, u_0, u_m1, ie, me, dy)
+    Fy = mE * ut
+    conv = conv + (Fy[:, 1:, :] - Fy[:, :-1, :]) / dy
+    # z: edges at back faces k, between u planes k-1 and k
+    rw = rzn * We                                            # (rho w) on w faces, extended rows
+    mZ = 0.5 * (rw + sh(rw, 1, X))
+    iz = iface | sh(iface, 1, Z)
+    iz = iz | sh(iz, 1, X)
+    mz_mu = 0.25 * (M + sh(M, 1, Z))
+    mz_mu = mz_mu + sh(mz_mu, 1, X)
+    ut = _advected(mZ, sh(Ue, 2, Z), sh(Ue, 1, Z), Ue, sh(Ue, -1, Z), Ue, sh(Ue, 1, Z), iz, mz_mu, dz)
+    Fz = mZ * ut
+    conv = conv + (sh(Fz, -1, Z) - Fz)[:, rows, :] / dz
+    # viscous
+    txx = M * (2.0 * (sh(Uve, -1, X) - Uve) / dx - (2.0 / 3.0) * Dv)
+    vis = (txx - sh(txx, 1, X))[:, rows, :] / dx
+    txy = me * ((Uve[:, J + 2, :] - Uve[:, J + 1, :]) / dy
+                + (vface(Vve, 0, ny + 1) - sh(vface(Vve, 0, ny + 1), 1, X)) / dx)
+    vis = vis + (txy[:, 1:, :] - txy[:, :-1, :]) / dy
+    txz = mz_mu * ((Uve - sh(Uve, 1, Z)) / dz + (Wve - sh(Wve, 1, X)) / dx)
+    vis = vis + (sh(txz, -1, Z) - txz)[:, rows, :] / dz
+    # surface tension
+    stx = (_faceavg(sh(sigma, 1, X), sigma) * _faceavg(sh(kappa, 1, X), kappa) * (C - sh(C, 1, X)) / dx)
+    if fsx is not None:
+        stx = stx + f(fsx)
+    r0, r1 = rxn[:, rows, :], rxn1[:, rows, :]
+    up = (r0 * u + dt * (-conv + vis + (r1 / rho_mean) * stx)) / r1
+
+    # ---------------- z momentum on w faces (x <-> z of the above) ---------
+    m = R * 0.5 * (We + sh(We, -1, Z))
+    wt = _advected(m, sh(We, 1, Z), We, sh(We, -1, Z), sh(We, -2, Z), sh(We, -1, Z), We, iface, M, dz)
+    Fzz = m * wt
+    conv = (Fzz - sh(Fzz, 1, Z))[:, rows, :] / dz
+    rvz = 0.5 * (rv + sh(rv, 1, Z))
+    w_m2, w_m1, w_0, w_p1 = (We[:, J + 2 + o, :] for o in (-2, -1, 0, 1))
+    iez = iface[:, J + 1, :] | iface[:, J + 2, :]
+    iez = iez | sh(iez, 1, Z)
+    mez = 0.25 * (M[:, J + 1, :] + M[:, J + 2, :])
+    mez = mez + sh(mez, 1, Z)
+    wt = _advected(rvz, w_m2, w_m1, w_0, w_p1, w_0, w_m1, iez, mez, dy)
+    Fy = rvz * wt
+    conv = conv + (Fy[:, 1:, :] - Fy[:, :-1, :]) / dy
+    ru = rxn * Ue                                            # (rho u) on u faces
+    mX = 0.5 * (ru + sh(ru, 1, Z))
+    wt = _advected(mX, sh(We, 2, X), sh(We, 1, X), We, sh(We, -1, X), We, sh(We, 1, X), iz, mz_mu, dx)
+    Fx = mX * wt
+    conv = conv + (sh(Fx, -1, X) - Fx)[:, rows, :] / dx
+    tzz = M * (2.0 * (sh(Wve, -1, Z) - Wve) / dz - (2.0 / 3.0) * Dv)
+    vis = (tzz - sh(tzz, 1, Z))[:, rows, :] / dz
+    tyz = mez * ((Wve[:, J + 2, :] - Wve[:, J + 1, :]) / dy
+                 + (vface(Vve, 0, ny + 1) - sh(vface(Vve, 0, ny + 1), 1, Z)) / dz)
+    vis = vis + (tyz[:, 1:, :] - tyz[:, :-1, :]) / dy
+    vis = vis + (sh(txz, -1, X) - txz)[:, rows, :] / dx
+    stz = (_faceavg(sh(sigma, 1, Z), sigma) * _faceavg(sh(kappa, 1, Z), kappa) * (C - sh(C, 1, Z)) / dz)
+    if fsz is not None:
+        stz = stz + f(fsz)
+    r0, r1 = rzn[:, rows, :], rzn1[:, rows, :]
+    wp = (r0 * w + dt * (-conv + vis + (r1 / rho_mean) * stz)) / r1
+
+    # ---------------- y momentum on v faces J = 1 .. ny (ny only for outflow)
+    Jv = np.arange(1, ny + 1)
+    # y: control-volume faces at cell centres j = J-1 (below) and J (above)
+    jc = np.arange(0, ny + 1)                                # centres 0..ny (ny is a ghost row)
+    mc = R[:, jc + 2, :] * 0.5 * (Ve[:, jc + 2, :] + Ve[:, jc + 3, :])
+    vt = _advected(mc, Ve[:, jc + 1, :], Ve[:, jc + 2, :], Ve[:, jc + 3, :],
+                   Ve[:, jc + 4, :], Ve[:, jc + 3, :], Ve[:, jc + 2, :], iface[:, jc + 2, :], M[:, jc + 2, :], dy)
+    Fc = mc * vt                                             # index = centre j
+    conv = (Fc[:, Jv, :] - Fc[:, Jv - 1, :]) / dy
+    # x: edges at u-face columns i, between v columns i-1 and i, rows J-1 and J
+    ru_e = rxn * Ue                                          # extended rows
+    mX = 0.5 * (ru_e[:, Jv + 1, :] + ru_e[:, Jv + 2, :])
+    Vr = Ve[:, Jv + 2, :]
+    iexy = iface[:, Jv + 1, :] | iface[:, Jv + 2, :]
+    iexy = iexy | sh(iexy, 1, X)
+    mexy = 0.25 * (M[:, Jv + 1, :] + M[:, Jv + 2, :])
+    mexy = mexy + sh(mexy, 1, X)
+    vt = _advected(mX, sh(Vr, 2, X), sh(Vr, 1, X), Vr, sh(Vr, -1, X), Vr, sh(Vr, 1, X), iexy, mexy, dx)
+    Fx = mX * vt
+    conv = conv + (sh(Fx, -1, X) - Fx) / dx
+    # z: edges at back faces k, rows J-1 and J
+    mZ = 0.5 * (rw[:, Jv + 1, :] + rw[:, Jv + 2, :])
+    iezy = iface[:, Jv + 1, :] | iface[:, Jv + 2, :]
+    iezy = iezy | sh(iezy, 1, Z)
+    mezy = 0.25 * (M[:, Jv + 1, :] + M[:, Jv + 2, :])
+    mezy = mezy + sh(mezy, 1, Z)
+    vt = _advected(mZ, sh(Vr, 2, Z), sh(Vr, 1, Z), Vr, sh(Vr, -1, Z), Vr, sh(Vr, 1, Z), iezy, mezy, dz)
+    Fz = mZ * vt
+    conv = conv + (sh(Fz, -1, Z) - Fz) / dz
+    # viscous
+    tyy = M[:, jc + 2, :] * (2.0 * (Vve[:, jc + 3, :] - Vve[:, jc + 2, :]) / dy - (2.0 / 3.0) * Dv[:, jc + 2, :])
+    vis = (tyy[:, Jv, :] - tyy[:, Jv - 1, :]) / dy
+    vis = vis + (sh(txy[:, Jv, :], -1, X) - txy[:, Jv, :]) / dx
+    vis = vis + (sh(tyz[:, Jv, :], -1, Z) - tyz[:, Jv, :]) / dz
+    Se, Ke = _mirror(sigma), _mirror(kappa)
+    sty = (_faceavg(Se[:, Jv + 1, :], Se[:, Jv + 2, :]) * _faceavg(Ke[:, Jv + 1, :], Ke[:, Jv + 2, :])
+           * (Ce[:, Jv + 2, :] - Ce[:, Jv + 1, :]) / dy)
+    if fsy is not None:
+        sty = sty + f(fsy)[:, Jv, :]
+    r0, r1 = yface_rho(1, ny + 1), yface_rho(1, ny + 1, n1=True)
+    vpi = (r0 * v[:, 1:, :] + dt * (-conv + vis + (r1 / rho_mean) * sty)) / r1
+    vp = v.copy()
+    vp[:, 1:ny, :] = vpi[:, :ny - 1, :]
+    if g.ybc == 1:
+        vp[:, ny, :] = vpi[:, ny - 1, :]
+    return up, vp, wp
