@@ -516,17 +516,21 @@ def split_fixed_point(g: Grid, rho0, dt, us, vs, ws, rho, pn, pnm1, S, iters, to
 
 def smart_face(U, Cc, D):
     """SMART value on a face from far-upwind U, upwind Cc and downwind D
-    (normalised variable phi_C = (Cc - U)/(D - U); bounded QUICK)."""
+    (bounded QUICK in the normalised variable phi_C = (Cc - U)/(D - U)):
+        0 < phi_C < 1/6    face = U + 3 (Cc - U)
+        1/6 <= phi_C < 5/6 face = U + (3/4)(Cc - U) + (3/8)(D - U)
+        5/6 <= phi_C < 1   face = D
+        otherwise          face = Cc (upwind)
+    The ranges are tested as products (a = Cc - U, d = D - U of equal sign,
+    6|a| against |d|), without forming the quotient."""
     U, Cc, D = np.broadcast_arrays(np.asarray(U, float), np.asarray(Cc, float), np.asarray(D, float))
-    den = D - U
-    with np.errstate(divide="ignore", invalid="ignore"):
-        ph = np.where(den != 0.0, (Cc - U) / np.where(den != 0.0, den, 1.0), -1.0)
-    pf = np.where((ph > 0) & (ph < 1.0 / 6.0), 3.0 * ph,
-         np.where((ph >= 1.0 / 6.0) & (ph < 5.0 / 6.0), 0.75 * ph + 0.375,
-         np.where((ph >= 5.0 / 6.0) & (ph < 1.0), 1.0, ph)))
-    out = U + pf * den
-    # outside 0 < phi_C < 1 (or flat data) the scheme is upwind
-    return np.where((ph > 0) & (ph < 1.0), out, Cc)
+    a = Cc - U
+    d = D - U
+    inside = (a * d > 0) & (np.abs(a) < np.abs(d))
+    low = 6.0 * np.abs(a) < np.abs(d)
+    mid = 6.0 * np.abs(a) < 5.0 * np.abs(d)
+    val = np.where(low, U + 3.0 * a, np.where(mid, U + 0.75 * a + 0.375 * d, D))
+    return np.where(inside, val, Cc)
 
 
 def _advected(m, Um, Cm, Dm, Up, Cp, Dp, iface, mu_face, h):
@@ -537,9 +541,8 @@ def _advected(m, Um, Cm, Dm, Up, Cp, Dp, iface, mu_face, h):
     Cc = np.where(pos, Cm, Cp)
     D = np.where(pos, Dm, Dp)
     s = smart_face(U, Cc, D)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        pe = np.abs(m) * h / mu_face
-    hyb = np.where(pe < 2.0, 0.5 * (Cc + D), Cc)
+    # cell Peclet number |m| h / mu below 2, tested without the quotient
+    hyb = np.where(np.abs(m) * h < 2.0 * mu_face, 0.5 * (Cc + D), Cc)
     return np.where(iface, hyb, s)
 
 

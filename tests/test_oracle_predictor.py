@@ -221,7 +221,7 @@ def _smart1(U, Cc, D):
 def _adv1(m, up_stencil, dn_stencil, iface, mu_f, h):
     U, Cc, D = up_stencil if m >= 0 else dn_stencil
     if iface:
-        return 0.5 * (Cc + D) if abs(m) * h / mu_f < 2.0 else Cc
+        return 0.5 * (Cc + D) if abs(m) * h < 2.0 * mu_f else Cc
     return _smart1(U, Cc, D)
 
 
