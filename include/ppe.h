@@ -195,6 +195,66 @@ ppe_status_t ppe_solve_varcoef(ppe_plan_t plan, const double* rho0, const double
                                const double* const* S, double* const* p, ppe_info_t* info,
                                int32_t max_iters, double tol, double* hist);
 
+/* Inputs of the predictor, Eq. (23) (Sec. 5.4), for one instance.  Device
+ * pointers, float64, layouts as above (u, uv, fsx like u; v, vv, fsy like v;
+ * w, wv, fsz like w; the rest cell fields).
+ *   u, v, w          : u^n (faces)
+ *   uv, vv, wv       : velocity used in the viscous term (the paper uses
+ *                      phase-wise velocities there); NULL = u^n, v^n, w^n
+ *   rho_n, rho_np1   : cell densities at times n and n+1
+ *   mu               : cell viscosity (> 0)
+ *   C                : volume fraction at n+1 (interface cells: 0 < C < 1)
+ *   sigma, kappa     : surface-tension coefficient and curvature, non-zero
+ *                      only in interface cells (Eq. 30 carries them to faces)
+ *   fsx, fsy, fsz    : tangential surface force grad_s(sigma)|grad C| on
+ *                      faces; NULL = none
+ *   rho_mean         : <rho> = (rho_G + rho_L)/2 of the CSF density scaling
+ *   dt               : time step (> 0) */
+typedef struct {
+  const double* u;
+  const double* v;
+  const double* w;
+  const double* uv;
+  const double* vv;
+  const double* wv;
+  const double* rho_n;
+  const double* rho_np1;
+  const double* mu;
+  const double* C;
+  const double* sigma;
+  const double* kappa;
+  const double* fsx;
+  const double* fsy;
+  const double* fsz;
+  double rho_mean;
+  double dt;
+} ppe_predict_t;
+
+/* Predictor, Eq. (23):
+ *   u^p = [ rho^n_f u^n + dt ( -div(rho u u)^n + div(tau)^n
+ *                              + (rho^{n+1}_f/<rho>)(sigma_f kappa_f grad C + f_s) ) ] / rho^{n+1}_f
+ * on the staggered finite volumes of Sec. 5.4:
+ *   - convection: SMART on every momentum control-volume face; where a cell
+ *     touching that face is an interface cell, central differences if the
+ *     cell Peclet number |m| h / mu < 2, else first-order upwind.  Mass flux
+ *     m: the mean of the two neighbouring face mass fluxes (rho_f times the
+ *     face velocity), or at a cell centre rho times the mean face velocity;
+ *   - viscous: tau = mu [grad u + grad u^T - (2/3)(div u) I] (Sec. 2) in
+ *     central differences; mu on edges is the mean of the four cells;
+ *   - surface tension: CSF with density scaling; sigma and kappa on faces by
+ *     Eq. (30), grad C the face difference;
+ *   - rho on faces: the mean of the two cells (as in the projection);
+ *   - y ends: ghost cells mirror the first two rows (cell fields, u, w); v
+ *     beyond a wall or symmetry face is 2 v_b - v, beyond an outflow face
+ *     v_ny.  Wall and symmetry faces of v keep v^n; an outflow face
+ *     (PPE_YBC_OUTFLOW) is predicted.
+ *   in         : host array of `batch` records
+ *   up, vp, wp : host arrays of `batch` device pointers (outputs, must not
+ *                alias an input)
+ * Needs ny >= 4 (else PPE_ERR_UNSUPPORTED). */
+ppe_status_t ppe_predict(ppe_plan_t plan, const ppe_predict_t* in, double* const* up, double* const* vp,
+                         double* const* wp);
+
 /* Pressure history resident in device memory, for time loops.  A ring holds
  * three pressure buffers per instance (p^{n-1}, p^n and the next pressure);
  * each step solves with p_hat = 2 p^n - p^{n-1} taken from the ring (Eq. 27),

@@ -52,11 +52,24 @@ INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("rho0_used", "<f8")
 assert INFO_DTYPE.itemsize == 64
 
 EXPORTS = ["ppe_plan_workspace_bytes", "ppe_plan", "ppe_plan_destroy", "ppe_plan_set_stream", "ppe_solve",
-           "ppe_correct", "ppe_residual", "ppe_source", "ppe_solve_varcoef", "ppe_ring_create", "ppe_ring_step",
+           "ppe_correct", "ppe_residual", "ppe_source", "ppe_predict", "ppe_solve_varcoef", "ppe_ring_create",
+           "ppe_ring_step",
            "ppe_ring_pressure", "ppe_ring_read", "ppe_ring_steps", "ppe_ring_destroy", "ppe_plan_profile",
            "ppe_plan_profile_read", "ppe_version"]
 
 SOURCE_FIELDS = ("C", "div_g", "div_l", "mdot", "area", "rho_g", "rho_l")
+
+
+PREDICT_FIELDS = ("u", "v", "w", "uv", "vv", "wv", "rho_n", "rho_np1", "mu", "C", "sigma", "kappa", "fsx", "fsy",
+                  "fsz")
+PREDICT_OPTIONAL = ("uv", "vv", "wv", "fsx", "fsy", "fsz")
+PREDICT_VFACE = ("v", "vv", "fsy")
+
+
+class PredictIn(ctypes.Structure):
+    """ppe_predict_t: device pointers of the Eq. (23) inputs of one instance."""
+    _fields_ = [(k, ctypes.c_void_p) for k in PREDICT_FIELDS] + [("rho_mean", ctypes.c_double),
+                                                                  ("dt", ctypes.c_double)]
 
 
 class Source(ctypes.Structure):
@@ -103,6 +116,8 @@ def load(path: str = LIB_PATH):
     lib.ppe_residual.restype = ctypes.c_int
     lib.ppe_source.argtypes = [P, ctypes.POINTER(Source), PP]
     lib.ppe_source.restype = ctypes.c_int
+    lib.ppe_predict.argtypes = [P, ctypes.POINTER(PredictIn), PP, PP, PP]
+    lib.ppe_predict.restype = ctypes.c_int
     lib.ppe_solve_varcoef.argtypes = [P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, P, ctypes.c_int32, ctypes.c_double,
                                       P]
     lib.ppe_solve_varcoef.restype = ctypes.c_int
@@ -315,6 +330,30 @@ class Plan:
         outs = self._batch(S, "S")
         _check(self.lib.ppe_source(self._h, recs, _ptrs(outs)), "ppe_source")
         return S
+
+    def predict(self, ins: Sequence[Dict], up, vp, wp):
+        """ppe_predict: u^p, v^p, w^p of Eq. (23) from the records `ins` (dicts
+        of float64 tensors named as PREDICT_FIELDS, optional ones may be absent,
+        plus 'rho_mean' and 'dt' floats)."""
+        if len(ins) != self.batch:
+            raise PPEError(f"predict: expected {self.batch} records, got {len(ins)}")
+        recs = (PredictIn * self.batch)()
+        for i, d in enumerate(ins):
+            for k in PREDICT_FIELDS:
+                t = d.get(k)
+                if t is None:
+                    if k in PREDICT_OPTIONAL:
+                        setattr(recs[i], k, None)
+                        continue
+                    raise PPEError(f"predict[{i}]: missing {k}")
+                chk = self._vface if k in PREDICT_VFACE else self._cell
+                setattr(recs[i], k, chk(t, f"{k}[{i}]").data_ptr())
+            recs[i].rho_mean = float(d["rho_mean"])
+            recs[i].dt = float(d["dt"])
+        st = self.lib.ppe_predict(self._h, recs, _ptrs(self._batch(up, "up")), _ptrs(self._batch(vp, "vp", v=True)),
+                                  _ptrs(self._batch(wp, "wp")))
+        _check(st, "ppe_predict")
+        return up, vp, wp
 
     def residual(self, u, v, w, S, out=None):
         """ppe_residual: per instance (||d - mean d||_2, max|d - mean d|, mean d), d = D u - S."""

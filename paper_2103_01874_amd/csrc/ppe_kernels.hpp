@@ -17,6 +17,8 @@
 //                the continuity residual of the result
 // and, before a solve when the caller assembles S through the library:
 //   k_source     S = (1-C) div_g + C div_l + m' (A/V0)(1/rho_g - 1/rho_l)  (Eq. 26)
+// and, producing u* itself:
+//   k_predict    the predictor u^p of Eq. (23)
 #pragma once
 
 #include "ppe_device.hpp"
@@ -68,6 +70,7 @@ struct Geom {
   int tws;              // log2 of the spectrum tile width (128-byte tiles of kx)
   long long npts;       // nx*ny*nz
   long long spec_elems; // ntiles * nz * ny * tile width (>= hx * ny * nz)
+  double dx, dy, dz;    // cell sizes
   double idx, idy, idz; // 1/dx, 1/dy, 1/dz
   double dy2;           // dy^2
   double inv_nxnz;      // 1/(nx*nz)

@@ -22,6 +22,7 @@
 #include "ppe_kernels.hpp"
 #include "ppe_kernels.hip.inc"
 #include "ppe_stencil.hip.inc"
+#include "ppe_predict.hip.inc"
 #include "ppe_plan_util.hpp"
 
 using namespace ppe;
@@ -182,6 +183,9 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   const long long ntile = (g.hx + (1 << g.tws) - 1) >> g.tws;
   g.spec_elems = (ntile << g.tws) * d.ny * d.nz;
   const double dx = d.lx / d.nx, dy = d.ly / d.ny, dz = d.lz / d.nz;
+  g.dx = dx;
+  g.dy = dy;
+  g.dz = dz;
   g.idx = 1.0 / dx;
   g.idy = 1.0 / dy;
   g.idz = 1.0 / dz;
@@ -996,6 +1000,54 @@ ppe_status_t ppe_ring_destroy(ppe_ring_t r) {
   for (int s = 0; s < 3; ++s) (void)hipFree(r->buf[s]);
   delete r;
   return PPE_OK;
+}
+
+ppe_status_t ppe_predict(ppe_plan_t p, const ppe_predict_t* in, double* const* up, double* const* vp,
+                         double* const* wp) {
+  if (!p || !in || !up || !vp || !wp) return PPE_ERR_ARG;
+  if (p->d.ny < 4) return PPE_ERR_UNSUPPORTED;
+  const int B = p->d.batch;
+  for (int i = 0; i < B; ++i) {
+    const ppe_predict_t& q = in[i];
+    if (!q.u || !q.v || !q.w || !q.rho_n || !q.rho_np1 || !q.mu || !q.C || !q.sigma || !q.kappa || !up[i] ||
+        !vp[i] || !wp[i])
+      return PPE_ERR_ARG;
+    if (!(q.dt > 0) || !std::isfinite(q.dt) || !(q.rho_mean > 0) || !std::isfinite(q.rho_mean)) return PPE_ERR_ARG;
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
+  const Geom& g = p->g;
+  const unsigned blocks = (unsigned)((g.npts + 255) / 256);
+  for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
+    const int nb = std::min(kMaxLaunch, B - i0);
+    PredTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    for (int i = 0; i < nb; ++i) {
+      const ppe_predict_t& q = in[i0 + i];
+      PredPtrs& t = tab.in[i];
+      t.u = q.u;
+      t.v = q.v;
+      t.w = q.w;
+      t.uv = q.uv ? q.uv : q.u;
+      t.vv = q.vv ? q.vv : q.v;
+      t.wv = q.wv ? q.wv : q.w;
+      t.rn = q.rho_n;
+      t.r1 = q.rho_np1;
+      t.mu = q.mu;
+      t.C = q.C;
+      t.sg = q.sigma;
+      t.kp = q.kappa;
+      t.fsx = q.fsx;
+      t.fsy = q.fsy;
+      t.fsz = q.fsz;
+      t.up = up[i0 + i];
+      t.vp = vp[i0 + i];
+      t.wp = wp[i0 + i];
+      t.rho_mean = q.rho_mean;
+      t.dt = q.dt;
+    }
+    PPE_TIMED(p, "k_predict", (k_predict<<<dim3(blocks, 1, nb), 256, 0, p->stream>>>(tab, g)));
+  }
+  return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
 }
 
 ppe_status_t ppe_plan_profile(ppe_plan_t p, int32_t enable) {

@@ -398,3 +398,29 @@ def sheet_sources(nx, ny, nz, *, seed, rho_l=640.0, rho_g=100.0, h0=0.3, nmodes=
 def sources_256(seed=7000) -> Sources:
     """256x128x256 sheet, rho 640/100: inputs of S."""
     return sheet_sources(256, 128, 256, seed=seed)
+
+
+# ---------------------------------------------------------------------------
+# Inputs of the predictor (Eq. 23) around a request's interface: viscosity,
+# volume fraction, surface tension and curvature.  Drawn, not computed.
+# ---------------------------------------------------------------------------
+
+def predictor_inputs(pr: Problem, seed: int, mu_l=2e-3, mu_g=2e-5, sigma=0.02, drho=0.02) -> Dict:
+    """Predictor inputs for request `pr`: u^n = its u*, v*, w*; rho^n = its rho;
+    rho^{n+1} = rho (1 + drho U(-1, 1)); C from rho (the generator's own
+    rho = rho_g + (rho_l - rho_g) C); mu = mu_g + (mu_l - mu_g) C; in interface
+    cells sigma = sigma (1 + 0.1 U(-1, 1)) and kappa = N(0, 1) / h0, zero
+    elsewhere; <rho> = (rho_g + rho_l)/2."""
+    rng = np.random.default_rng(seed)
+    rl, rg = pr.meta["rho_l"], pr.meta["rho_g"]
+    C = (pr.rho - rg) / (rl - rg)
+    iface = (C > 0.0) & (C < 1.0)
+    n = int(iface.sum())
+    sg = np.zeros(C.shape)
+    kp = np.zeros(C.shape)
+    sg[iface] = sigma * (1.0 + 0.1 * rng.uniform(-1.0, 1.0, size=n))
+    kp[iface] = rng.standard_normal(n) / pr.meta.get("h0", 0.3)
+    return {"u": pr.us, "v": pr.vs, "w": pr.ws, "rho_n": pr.rho,
+            "rho_np1": pr.rho * (1.0 + drho * rng.uniform(-1.0, 1.0, size=C.shape)),
+            "mu": mu_g + (mu_l - mu_g) * C, "C": C, "sigma": sg, "kappa": kp,
+            "rho_mean": 0.5 * (rg + rl), "dt": pr.dt}
