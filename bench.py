@@ -43,6 +43,10 @@ WORKLOADS = {
                                    "FP64: target divergence from Eq. (26) inputs (phase compressibilities, "
                                    "interface mass flux, under-resolved block) + direct solve + correction, "
                                    "256x128x256 liquid sheet rho 640/100"),
+    "fullstep_256x128x256_fp64": ("sheet_256", 0, 0,
+                                  "FP64 flow step from u^n: predictor (Eq. 23: SMART convection, viscous stress, "
+                                  "CSF) + target divergence (Eq. 26) + direct solve + correction, 256x128x256 "
+                                  "liquid sheet rho 640/100"),
     "timeloop_256x128x256_fp64": ("sheet_256", 0, 0,
                                   "FP64 direct solve + correction in a time loop: p^n, p^{n-1} resident in a "
                                   "device ring, 256x128x256 liquid sheet rho 640/100"),
@@ -95,6 +99,8 @@ def algorithmic_bytes(kernel: str, nx: int, ny: int, nz: int, precision: int, mo
         # C and one phase divergence -> S everywhere; interface cells also read
         # the other divergence, m', A/V0, rho_g, rho_l (8 B each) and the mask (1 B)
         "k_source": 24 * N + 41 * n_iface,
+        # u^n, v^n, w^n, rho^n, rho^{n+1}, mu, C, sigma, kappa -> u^p, v^p, w^p
+        "k_predict": 8 * (8 * N + Nv) + 8 * (2 * N + Nv),
     }
     return float(table.get(kernel, 0.0))
 
@@ -320,8 +326,15 @@ def main():
     g = lambda k: [fields[k]]
     o = lambda k: [outs[k]]
     src_dev = None
+    pred_dev = None
     n_iface = 0
-    if "_src_" in args.workload:
+    if args.workload.startswith("fullstep"):
+        rin = synth.predictor_inputs(pr, pr.meta["seed"] + 53)
+        with torch.cuda.stream(stream):
+            pred_dev = {k: (torch.from_numpy(np.ascontiguousarray(v)).to(dev) if isinstance(v, np.ndarray) else v)
+                        for k, v in rin.items()}
+        torch.cuda.synchronize()
+    if "_src_" in args.workload or args.workload.startswith("fullstep"):
         # Eq. (26) inputs around the same interface as the density field
         rl, rg = pr.meta["rho_l"], pr.meta["rho_g"]
         C = (pr.rho - rg) / (rl - rg)
@@ -349,6 +362,9 @@ def main():
         one_step = None
 
     def split_step():
+        if pred_dev is not None:
+            # u^p into the u* buffers of the projection
+            plan.predict([pred_dev], g("us"), g("vs"), g("ws"))
         if src_dev is not None:
             plan.source([src_dev], g("S"))
         plan.solve([pr.rho0], [pr.dt], g("us"), g("vs"), g("ws"), g("rho"), g("pn"), g("pnm1"), g("S"), o("p"),
