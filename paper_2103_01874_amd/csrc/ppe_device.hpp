@@ -263,6 +263,45 @@ PPE_HD void stage_write(BufT* buf, int es, int t, int st, const FftDev& f, const
   }
 }
 
+// The read half of stage 0 from a loader instead of LDS: v[q R + r] =
+// load(j + r n/R) for the thread's butterflies j = t + tc q.
+template <int E, int R, typename T, typename LoadF>
+PPE_HD void stage_load(int t, const FftDev& f, LoadF load, cplx<T>* v) {
+  constexpr int NB = E / R;
+  const int nr = f.n / R;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int j = t + f.tc * q;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[q * R + r] = load(j + r * nr);
+  }
+}
+
+// The write half of a stage to a storer instead of LDS: store(n, x) for the
+// stage's outputs n (same twiddles and butterflies as stage_write).
+template <int E, int R, int DIR, typename T, typename StoreF>
+PPE_HD void stage_store(int t, int st, const FftDev& f, const double* tw, cplx<T>* v, StoreF store) {
+  constexpr int NB = E / R;
+  const int ns = f.ns[st];
+  const int span = ns * R;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int j = t + f.tc * q;
+    int jd, jm;
+    fast_divmod(j, ns, f.inv_ns[st], jd, jm);
+    if (ns > 1) {
+      cplx<T> w[R];
+      stage_twiddles_of<R, DIR, T>(tw, jm * f.tstep[st], w);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], w[r]);
+    }
+    dft<R, DIR>(&v[q * R]);
+    const int base = jd * span + jm;
+#pragma unroll
+    for (int r = 0; r < R; ++r) store(base + r * ns, v[q * R + r]);
+  }
+}
+
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
 // Copy the twiddle table of `f` into LDS (all threads of the block; the
 // caller's next barrier publishes it).
@@ -305,6 +344,85 @@ __device__ __forceinline__ void fft_lds(BufT* buf, int es, int t, bool active, c
     }
     __syncthreads();
   }
+}
+
+// Whole transform whose first stage reads its inputs through load(n) (global
+// memory) instead of LDS and, with GSTORE, whose last stage hands its outputs
+// to store(n, x) instead of writing LDS.  Compared with staging the data in
+// LDS first and copying it out after fft_lds, this saves two LDS passes and
+// two barriers.  Every thread of the block must call it; threads with
+// active == false only join the barriers.  Without GSTORE the result is in
+// buf (padded or strided as for fft_lds) after the final barrier.  With
+// GSTORE, buf is dead on return and a caller reusing LDS needs a barrier.
+template <int E, int DIR, bool PAD, bool GSTORE, typename T, typename BufT, typename LoadF, typename StoreF>
+__device__ __forceinline__ void fft_io(BufT* buf, int es, int t, bool active, const FftDev& f, const double* tw,
+                                       LoadF load, StoreF store) {
+  cplx<T> v[E];
+  const int last = f.nst - 1;
+  if (last < 0) {  // length 1: the transform is the identity
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int n = t + f.tc * q;
+        const cplx<T> x = load(n);
+        if constexpr (GSTORE) store(n, x);
+        else buf[lslot<PAD>(n, es)] = x;
+      }
+    }
+    if constexpr (!GSTORE) __syncthreads();
+    return;
+  }
+#define PPE_FFT_IO_DISPATCH(...)                          \
+  {                                                      \
+    const int R_ = f.radix[s];                           \
+    if (R_ == 8) {                                       \
+      if constexpr (E % 8 == 0) {                        \
+        constexpr int R = 8;                             \
+        __VA_ARGS__                                      \
+      }                                                  \
+    } else if (R_ == 4) {                                \
+      if constexpr (E % 4 == 0) {                        \
+        constexpr int R = 4;                             \
+        __VA_ARGS__                                      \
+      }                                                  \
+    } else if (R_ == 3) {                                \
+      if constexpr (E % 3 == 0) {                        \
+        constexpr int R = 3;                             \
+        __VA_ARGS__                                      \
+      }                                                  \
+    } else {                                             \
+      if constexpr (E % 2 == 0) {                        \
+        constexpr int R = 2;                             \
+        __VA_ARGS__                                      \
+      }                                                  \
+    }                                                    \
+  }
+  {
+    const int s = 0;
+    PPE_FFT_IO_DISPATCH({
+      if (active) stage_load<E, R, T>(t, f, load, v);
+      if (GSTORE && last == 0) {
+        if (active) stage_store<E, R, DIR, T>(t, 0, f, tw, v, store);
+      } else {
+        if (active) stage_write<E, R, DIR, PAD, T>(buf, es, t, 0, f, tw, v);
+      }
+    })
+  }
+  if (GSTORE && last == 0) return;
+  __syncthreads();
+  for (int s = 1; s <= last; ++s) {
+    PPE_FFT_IO_DISPATCH({
+      if (active) stage_read<E, R, PAD, T>(buf, es, t, f, v);
+      if (GSTORE && s == last) {
+        if (active) stage_store<E, R, DIR, T>(t, s, f, tw, v, store);
+      } else {
+        __syncthreads();
+        if (active) stage_write<E, R, DIR, PAD, T>(buf, es, t, s, f, tw, v);
+        __syncthreads();
+      }
+    })
+  }
+#undef PPE_FFT_IO_DISPATCH
 }
 #endif
 
