@@ -55,7 +55,6 @@ template <int MC>
 void run_tri(int ny, int P, double s, int zero, int outflow, const double* rhs, double* x) {
   std::vector<RedRow<double>> red(2 * (size_t)P);
   std::vector<cplx<double>> r((size_t)P * MC);
-  std::vector<double> phi((size_t)P * MC), psi((size_t)P * MC);
   std::vector<int> j0v(P), mv(P);
   for (int p = 0; p < P; ++p) {
     const int j0 = (int)(((long long)p * ny) / P);
@@ -67,9 +66,10 @@ void run_tri(int ny, int P, double s, int zero, int outflow, const double* rhs, 
     for (int i = 0; i < MC; ++i) rr[i] = mk(0.0, 0.0);
     for (int i = 0; i < m; ++i) rr[i] = mk(rhs[2 * (j0 + i)], rhs[2 * (j0 + i) + 1]);
     const cplx<double> rf = rr[0], rl = rr[m - 1];
-    chunk_eliminate<MC>(rr, m, s, &phi[(size_t)p * MC], &psi[(size_t)p * MC]);
+    ChunkEnds<double> e;
+    chunk_eliminate<MC>(rr, m, s, e);
     RedRow<double> f, l;
-    chunk_reduced_rows<MC>(rr, rf, rl, m, s, p == 0, p == P - 1, outflow != 0, &phi[(size_t)p * MC], &psi[(size_t)p * MC], f, l);
+    chunk_reduced_rows<MC>(rr, rf, rl, m, s, p == 0, p == P - 1, outflow != 0, e, f, l);
     if (zero && p == 0) {
       f.a = 0.0;
       f.b = 1.0;
@@ -90,12 +90,10 @@ void run_tri(int ny, int P, double s, int zero, int outflow, const double* rhs, 
     const cplx<double> xl = red[2 * p + 1].d;
     const int m = mv[p], j0 = j0v[p];
     cplx<double>* rr = &r[(size_t)p * MC];
-    const double* ph = &phi[(size_t)p * MC];
-    const double* ps = &psi[(size_t)p * MC];
+    chunk_interior<MC>(rr, m, s, xf, xl);
     for (int i = 1; i < m - 1; ++i) {
-      const int q = i - 1;
-      x[2 * (j0 + i)] = rr[i].re + ph[q] * xf.re + ps[q] * xl.re;
-      x[2 * (j0 + i) + 1] = rr[i].im + ph[q] * xf.im + ps[q] * xl.im;
+      x[2 * (j0 + i)] = rr[i].re;
+      x[2 * (j0 + i) + 1] = rr[i].im;
     }
     x[2 * j0] = xf.re;
     x[2 * j0 + 1] = xf.im;

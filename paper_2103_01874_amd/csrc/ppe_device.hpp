@@ -444,43 +444,91 @@ __device__ __forceinline__ void fft_io(BufT* buf, int es, int t, bool active, co
 // ---------------------------------------------------------------------------
 constexpr int kMaxChunk = 16;   // longest chunk the kernels instantiate
 
-// Interior elimination, in place.  On entry r[0..m-1] holds the chunk's
-// scaled right-hand side; on exit r[1..m-2] holds y, phi[0..m-3] and
-// psi[0..m-3] the two homogeneous solutions (r[0], r[m-1] are untouched).
+// Pivots of the interior rows (ni = m - 2 of them): q_i = 1/(1+g_i) and the
+// forward product fphi_i = q_0 ... q_i.  They depend on s and ni only.
 template <int MC, typename T>
-PPE_HD void chunk_eliminate(cplx<T>* r, int m, T s, T* phi, T* psi) {
-  const int ni = m - 2;
-  if (ni <= 0) return;
-  T q[MC];  // 1/(1+g_i)
+PPE_HD void chunk_pivots(int ni, T s, T* q, T* fphi) {
   T g = T(1) + s;
-  // forward sweep: dp_i = (dp_{i-1} - r_i) q_i (den_i = -(1+g_i)); fphi_i = fphi_{i-1} q_i
 #pragma unroll
   for (int i = 0; i < MC - 2; ++i) {
     if (i < ni) {
       if (i > 0) g = s + g * q[i - 1];
-      const T qi = rcp_nr(T(1) + g);
-      q[i] = qi;
-      const cplx<T> ri = r[i + 1];
-      if (i == 0) {
-        r[1] = mk(-ri.re * qi, -ri.im * qi);
-        phi[0] = qi;
-      } else {
-        r[i + 1] = mk((r[i].re - ri.re) * qi, (r[i].im - ri.im) * qi);
-        phi[i] = phi[i - 1] * qi;
-      }
+      q[i] = rcp_nr(T(1) + g);
+      fphi[i] = i == 0 ? q[0] : fphi[i - 1] * q[i];
     }
   }
-  // backward sweep: x_i = dp_i + x_{i+1} q_i ; psi_last = q_last, psi_i = psi_{i+1} q_i
+}
+
+// The homogeneous solutions at the chunk's two interior end rows (local rows
+// 1 and m-2); with fewer than one interior row they are not used.
+template <typename T>
+struct ChunkEnds {
+  T phi1, psi1, phiL, psiL;
+};
+
+// Interior elimination, in place.  On entry r[0..m-1] holds the chunk's
+// scaled right-hand side; on exit r[1..m-2] holds y and `e` the end values of
+// phi and psi (r[0], r[m-1] are untouched).  The full phi_i, psi_i are not
+// kept: chunk_interior forms them again from s when the chunk's end values
+// are known.
+//   forward:  dp_i = (dp_{i-1} - r_i) q_i   (den_i = -(1+g_i))
+//   backward: y_i = dp_i + y_{i+1} q_i;  phi_i = fphi_i + phi_{i+1} q_i;
+//             psi_i = psi_{i+1} q_i, with phi_last = fphi_last, psi_last = q_last
+template <int MC, typename T>
+PPE_HD void chunk_eliminate(cplx<T>* r, int m, T s, ChunkEnds<T>& e) {
+  const int ni = m - 2;
+  if (ni <= 0) return;
+  T q[MC], fphi[MC];
+  chunk_pivots<MC>(ni, s, q, fphi);
+#pragma unroll
+  for (int i = 0; i < MC - 2; ++i) {
+    if (i < ni) {
+      const cplx<T> ri = r[i + 1];
+      if (i == 0) r[1] = mk(-ri.re * q[0], -ri.im * q[0]);
+      else r[i + 1] = mk((r[i].re - ri.re) * q[i], (r[i].im - ri.im) * q[i]);
+    }
+  }
+  T ph = T(0), ps = T(0);
 #pragma unroll
   for (int i = MC - 3; i >= 0; --i) {
     if (i < ni) {
       if (i == ni - 1) {
-        psi[i] = q[i];
+        ph = fphi[i];
+        ps = q[i];
+        e.phiL = ph;
+        e.psiL = ps;
       } else {
         r[i + 1] = mk(r[i + 1].re + r[i + 2].re * q[i], r[i + 1].im + r[i + 2].im * q[i]);
-        phi[i] = phi[i] + phi[i + 1] * q[i];
-        psi[i] = psi[i + 1] * q[i];
+        ph = fphi[i] + ph * q[i];
+        ps = ps * q[i];
       }
+    }
+  }
+  e.phi1 = ph;
+  e.psi1 = ps;
+}
+
+// x_i = y_i + phi_i x_first + psi_i x_last for the interior rows, in place,
+// with phi_i and psi_i formed as in chunk_eliminate (same operations, same
+// order, so the same values).
+template <int MC, typename T>
+PPE_HD void chunk_interior(cplx<T>* r, int m, T s, const cplx<T>& xf, const cplx<T>& xl) {
+  const int ni = m - 2;
+  if (ni <= 0) return;
+  T q[MC], fphi[MC];
+  chunk_pivots<MC>(ni, s, q, fphi);
+  T ph = T(0), ps = T(0);
+#pragma unroll
+  for (int i = MC - 3; i >= 0; --i) {
+    if (i < ni) {
+      if (i == ni - 1) {
+        ph = fphi[i];
+        ps = q[i];
+      } else {
+        ph = fphi[i] + ph * q[i];
+        ps = ps * q[i];
+      }
+      r[i + 1] = mk(r[i + 1].re + ph * xf.re + ps * xl.re, r[i + 1].im + ph * xf.im + ps * xl.im);
     }
   }
 }
@@ -497,8 +545,8 @@ struct RedRow {
 
 template <int MC, typename T>
 PPE_HD void chunk_reduced_rows(const cplx<T>* r, const cplx<T>& r_first, const cplx<T>& r_last, int m, T s,
-                               bool global_first, bool global_last, bool top_outflow, const T* phi,
-                               const T* psi, RedRow<T>& f, RedRow<T>& l) {
+                               bool global_first, bool global_last, bool top_outflow, const ChunkEnds<T>& e,
+                               RedRow<T>& f, RedRow<T>& l) {
   const T beta_first = global_first ? (-T(1) - s) : (-T(2) - s);
   const T beta_last = global_last ? ((top_outflow ? -T(3) : -T(1)) - s) : (-T(2) - s);
   const int ni = m - 2;
@@ -506,16 +554,14 @@ PPE_HD void chunk_reduced_rows(const cplx<T>* r, const cplx<T>& r_first, const c
   T phi1 = T(0), psi1 = T(1), phiL = T(1), psiL = T(0);
   cplx<T> y1 = mk(T(0), T(0)), yL = mk(T(0), T(0));
   if (ni > 0) {
-    phi1 = phi[0];
-    psi1 = psi[0];
+    phi1 = e.phi1;
+    psi1 = e.psi1;
+    phiL = e.phiL;
+    psiL = e.psiL;
     y1 = r[1];
 #pragma unroll
     for (int i = 0; i < MC - 2; ++i)
-      if (i == ni - 1) {
-        phiL = phi[i];
-        psiL = psi[i];
-        yL = r[i + 1];
-      }
+      if (i == ni - 1) yL = r[i + 1];
   }
   f.a = global_first ? T(0) : T(1);
   f.b = beta_first + phi1;

@@ -86,6 +86,17 @@ __host__ __device__ __forceinline__ long long sidx(const Geom& g, int kx, long l
   return ((t * g.nz * g.ny + row) << g.tws) + (kx & ((1 << g.tws) - 1));
 }
 
+// The tile shift of a spectrum of TS values, as a constant (g.tws at run time).
+template <typename TS>
+constexpr int kTileShift = sizeof(TS) == 8 ? 3 : 4;
+
+template <typename TS>
+__host__ __device__ __forceinline__ long long sidx_t(const Geom& g, int kx, long long row) {
+  constexpr int sh = kTileShift<TS>;
+  const long long t = kx >> sh;
+  return ((t * g.nz * g.ny + row) << sh) + (kx & ((1 << sh) - 1));
+}
+
 // Workspace seen by the kernels (device pointers, per-instance strides).
 template <typename TS>
 struct Work {

@@ -406,13 +406,20 @@ ppe_status_t launch_chain(ppe_plan_s* p, const Work<TS>& W, int nb, int check) {
   if (st != PPE_OK) return st;
   dim3 tgrid((g.hx + p->txs - 1) / p->txs, g.nz, nb);
   dim3 tblock(p->txs * p->pch);
+  const bool full = g.ny == p->pch * p->mc;
   PPE_TIMED(p, "k_tri", {
-    if (p->mc == 4)
-      k_tri<TS, 4><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+    if (p->mc == 4 && full)
+      k_tri<TS, 4, true><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+    else if (p->mc == 4)
+      k_tri<TS, 4, false><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+    else if (p->mc == 8 && full)
+      k_tri<TS, 8, true><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
     else if (p->mc == 8)
-      k_tri<TS, 8><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+      k_tri<TS, 8, false><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+    else if (full)
+      k_tri<TS, 16, true><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
     else
-      k_tri<TS, 16><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+      k_tri<TS, 16, false><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
   });
   return launch_fft_z<TS>(p, W, nb, +1, check);
 }
