@@ -36,19 +36,43 @@ void run_fft(const HostFft& h, const std::vector<double>& tw, cplx<double>* buf)
     // read half for every thread, then write half for every thread
     for (int t = 0; t < f.tc; ++t) {
       cplx<double>* v = &regs[(size_t)t * E];
-      if constexpr (E % 8 == 0) if (R == 8) stage_read<E, 8, PAD, double>(buf, 1, t, f, v);
-      if constexpr (E % 4 == 0) if (R == 4) stage_read<E, 4, PAD, double>(buf, 1, t, f, v);
-      if constexpr (E % 3 == 0) if (R == 3) stage_read<E, 3, PAD, double>(buf, 1, t, f, v);
-      if constexpr (E % 2 == 0) if (R == 2) stage_read<E, 2, PAD, double>(buf, 1, t, f, v);
+      if constexpr (E % 8 == 0) if (R == 8) stage_read<E, 8, PAD, double>(buf, 1, t, RtStage{f, s}, v);
+      if constexpr (E % 4 == 0) if (R == 4) stage_read<E, 4, PAD, double>(buf, 1, t, RtStage{f, s}, v);
+      if constexpr (E % 3 == 0) if (R == 3) stage_read<E, 3, PAD, double>(buf, 1, t, RtStage{f, s}, v);
+      if constexpr (E % 2 == 0) if (R == 2) stage_read<E, 2, PAD, double>(buf, 1, t, RtStage{f, s}, v);
     }
     for (int t = 0; t < f.tc; ++t) {
       cplx<double>* v = &regs[(size_t)t * E];
-      if constexpr (E % 8 == 0) if (R == 8) stage_write<E, 8, DIR, PAD, double>(buf, 1, t, s, f, f.tw, v);
-      if constexpr (E % 4 == 0) if (R == 4) stage_write<E, 4, DIR, PAD, double>(buf, 1, t, s, f, f.tw, v);
-      if constexpr (E % 3 == 0) if (R == 3) stage_write<E, 3, DIR, PAD, double>(buf, 1, t, s, f, f.tw, v);
-      if constexpr (E % 2 == 0) if (R == 2) stage_write<E, 2, DIR, PAD, double>(buf, 1, t, s, f, f.tw, v);
+      if constexpr (E % 8 == 0) if (R == 8) stage_write<E, 8, DIR, PAD, double>(buf, 1, t, RtStage{f, s}, f.tw, v);
+      if constexpr (E % 4 == 0) if (R == 4) stage_write<E, 4, DIR, PAD, double>(buf, 1, t, RtStage{f, s}, f.tw, v);
+      if constexpr (E % 3 == 0) if (R == 3) stage_write<E, 3, DIR, PAD, double>(buf, 1, t, RtStage{f, s}, f.tw, v);
+      if constexpr (E % 2 == 0) if (R == 2) stage_write<E, 2, DIR, PAD, double>(buf, 1, t, RtStage{f, s}, f.tw, v);
     }
   }
+}
+
+// The same transform through a compile-time plan (CtStage), stage by stage.
+template <int N, int S, int DIR>
+void run_fft_ct(const std::vector<double>& tw, cplx<double>* buf, std::vector<cplx<double>>& regs) {
+  constexpr int E = CFft<N>::e;
+  constexpr int R = CFft<N>::tab.radix[S];
+  const CtStage<N, S> sp;
+  for (int t = 0; t < CFft<N>::tc; ++t) stage_read<E, R, true, double>(buf, 1, t, sp, &regs[(size_t)t * E]);
+  for (int t = 0; t < CFft<N>::tc; ++t)
+    stage_write<E, R, DIR, true, double>(buf, 1, t, sp, tw.data(), &regs[(size_t)t * E]);
+  if constexpr (S + 1 < CFft<N>::nst) run_fft_ct<N, S + 1, DIR>(tw, buf, regs);
+}
+
+// 0 if CFft<N> has the host plan's stages (radix, ns, tstep), e and tc.
+template <int N>
+int ct_plan_check() {
+  HostFft h;
+  if (!fft_factor(N, h)) return -1;
+  if (h.e != CFft<N>::e || h.tc != CFft<N>::tc || h.nst != CFft<N>::nst) return -2;
+  for (int s = 0; s < h.nst; ++s)
+    if (h.radix[s] != CFft<N>::tab.radix[s] || h.ns[s] != CFft<N>::tab.ns[s] || h.tstep[s] != CFft<N>::tab.tstep[s])
+      return -3;
+  return 0;
 }
 
 template <int MC>
@@ -163,6 +187,51 @@ int hc_fft(int n, int dir, const double* in, double* out) {
     out[2 * i + 1] = buf[lslot<true>(i, 1)].im;
   }
   return 0;
+}
+
+// hc_fft through the compile-time plan of a power-of-two n in 16..2048.
+int hc_fft_ct(int n, int dir, const double* in, double* out) {
+  std::vector<double> tw = twiddles(n);
+  std::vector<cplx<double>> buf(padded_len(n)), regs((size_t)n);
+  for (int i = 0; i < n; ++i) buf[lslot<true>(i, 1)] = mk(in[2 * i], in[2 * i + 1]);
+#define HC_CT(NN)                                                   \
+  case NN:                                                          \
+    if (dir < 0) run_fft_ct<NN, 0, -1>(tw, buf.data(), regs);       \
+    else run_fft_ct<NN, 0, +1>(tw, buf.data(), regs);               \
+    break;
+  switch (n) {
+    HC_CT(16)
+    HC_CT(32)
+    HC_CT(64)
+    HC_CT(128)
+    HC_CT(256)
+    HC_CT(512)
+    HC_CT(1024)
+    HC_CT(2048)
+    default:
+      return -1;
+  }
+#undef HC_CT
+  for (int i = 0; i < n; ++i) {
+    out[2 * i] = buf[lslot<true>(i, 1)].re;
+    out[2 * i + 1] = buf[lslot<true>(i, 1)].im;
+  }
+  return 0;
+}
+
+// 0 if the compile-time plan of n equals the host factorisation.
+int hc_ct_plan_check(int n) {
+  switch (n) {
+    case 16: return ct_plan_check<16>();
+    case 32: return ct_plan_check<32>();
+    case 64: return ct_plan_check<64>();
+    case 128: return ct_plan_check<128>();
+    case 256: return ct_plan_check<256>();
+    case 512: return ct_plan_check<512>();
+    case 1024: return ct_plan_check<1024>();
+    case 2048: return ct_plan_check<2048>();
+    default: return -1;
+  }
 }
 
 // One y system: x_{j-1} + beta_j x_j + x_{j+1} = rhs_j (scaled form, complex

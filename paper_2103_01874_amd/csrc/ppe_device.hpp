@@ -85,6 +85,90 @@ struct FftDev {
                            // (global table; kernels stage a copy in LDS)
 };
 
+// Compile-time plan of a power-of-two length N (2 <= N <= 2048), factored as
+// the host factors powers of two: radix-8 stages, then one radix-4 or radix-2
+// stage for the remaining factor.  Stage counts, radices, sub-transform
+// lengths and twiddle steps are constants, so the stage loop unrolls, the
+// radix dispatch folds away and j / ns, j mod ns become shifts.  Only the
+// twiddle table is a run-time value.
+struct StageTab {
+  int radix[kMaxStages];
+  int ns[kMaxStages];
+  int tstep[kMaxStages];
+};
+
+constexpr int ilog2_c(int x) { return x <= 1 ? 0 : 1 + ilog2_c(x / 2); }
+
+constexpr StageTab pow2_stages(int n) {
+  StageTab t{};
+  const int lg = ilog2_c(n);
+  int ns = 1, s = 0;
+  for (int k = 0; k < lg / 3; ++k, ++s) {
+    t.radix[s] = 8;
+    t.ns[s] = ns;
+    t.tstep[s] = n / (ns * 8);
+    ns *= 8;
+  }
+  if (lg % 3) {
+    const int r = 1 << (lg % 3);
+    t.radix[s] = r;
+    t.ns[s] = ns;
+    t.tstep[s] = n / (ns * r);
+  }
+  return t;
+}
+
+template <int N>
+struct CFft {
+  static_assert(N >= 2 && (N & (N - 1)) == 0, "power of two");
+  static constexpr int n = N;
+  static constexpr int nst = ilog2_c(N) / 3 + (ilog2_c(N) % 3 ? 1 : 0);
+  static constexpr int e = ilog2_c(N) >= 3 ? 8 : N;  // lcm of the radices
+  static constexpr int tc = N / e;
+  static constexpr StageTab tab = pow2_stages(N);
+  const double* tw;  // as in FftDev
+};
+
+// What one Stockham stage needs of its plan: the transform length, threads
+// per transform, the sub-transform length ns before the stage, the twiddle
+// step, and j / ns, j mod ns.  RtStage reads a run-time plan; CtStage<N, S>
+// is stage S of CFft<N>, all constants.
+struct RtStage {
+  const FftDev& f;
+  int st;
+  PPE_HD int n() const { return f.n; }
+  PPE_HD int tc() const { return f.tc; }
+  PPE_HD int ns() const { return f.ns[st]; }
+  PPE_HD int tstep() const { return f.tstep[st]; }
+  // j / ns and j mod ns for 0 <= j < 2^24 from a float quotient estimate,
+  // corrected to the exact integers
+  PPE_HD void divmod(int j, int& q, int& r) const {
+    const int d = f.ns[st];
+    q = (int)((float)j * f.inv_ns[st]);
+    r = j - q * d;
+    if (r < 0) {
+      q -= 1;
+      r += d;
+    } else if (r >= d) {
+      q += 1;
+      r -= d;
+    }
+  }
+};
+
+template <int N, int S>
+struct CtStage {
+  static constexpr int kNs = CFft<N>::tab.ns[S];
+  PPE_HD static constexpr int n() { return N; }
+  PPE_HD static constexpr int tc() { return CFft<N>::tc; }
+  PPE_HD static constexpr int ns() { return kNs; }
+  PPE_HD static constexpr int tstep() { return CFft<N>::tab.tstep[S]; }
+  PPE_HD static void divmod(int j, int& q, int& r) {
+    q = (int)((unsigned)j / (unsigned)kNs);
+    r = (int)((unsigned)j % (unsigned)kNs);
+  }
+};
+
 // Small DFTs on registers.  DIR = -1 forward (exp(-i...)), +1 inverse.
 template <int DIR, typename T>
 PPE_HD void dft2(cplx<T>* v) {
@@ -182,33 +266,20 @@ PPE_HD int padded_len(int n) { return n + (n >> kRowPadShift) + 1; }
 //   element n of the transform lives at buf[lslot(n, es)]
 //   butterfly j in [0, n/R): inputs j + r n/R, twiddle exp(DIR 2 pi i r (j mod Ns)/(Ns R)),
 //   outputs (j / Ns) Ns R + (j mod Ns) + r Ns.
-// Thread t owns butterflies j = t + tc q, q in [0, E/R).
-template <int E, int R, bool PAD, typename T, typename BufT>
-PPE_HD void stage_read(const BufT* buf, int es, int t, const FftDev& f, cplx<T>* v) {
+// Thread t owns butterflies j = t + tc q, q in [0, E/R).  `sp` describes the
+// stage (RtStage or CtStage).
+template <int E, int R, bool PAD, typename T, typename BufT, typename SP>
+PPE_HD void stage_read(const BufT* buf, int es, int t, const SP& sp, cplx<T>* v) {
   constexpr int NB = E / R;
-  const int nr = f.n / R;
+  const int nr = sp.n() / R;
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int j = t + f.tc * q;
+    const int j = t + sp.tc() * q;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const BufT x = buf[lslot<PAD>(j + r * nr, es)];
       v[q * R + r] = mk(T(x.re), T(x.im));
     }
-  }
-}
-
-// j / ns and j mod ns for 0 <= j < 2^24 from a float quotient estimate,
-// corrected to the exact integers.
-PPE_HD void fast_divmod(int j, int ns, float inv_ns, int& q, int& r) {
-  q = (int)((float)j * inv_ns);
-  r = j - q * ns;
-  if (r < 0) {
-    q -= 1;
-    r += ns;
-  } else if (r >= ns) {
-    q += 1;
-    r -= ns;
   }
 }
 
@@ -234,44 +305,48 @@ PPE_HD void stage_twiddles_of(const double* tw, int base, cplx<T>* w) {
   }
 }
 
-template <int E, int R, int DIR, bool PAD, typename T, typename BufT>
-PPE_HD void stage_write(BufT* buf, int es, int t, int st, const FftDev& f, const double* tw, cplx<T>* v) {
+// Twiddles and butterflies of the thread's group q; returns the index of
+// output r = 0 (the others follow at stride ns).
+template <int R, int DIR, typename T, typename SP>
+PPE_HD int stage_butterfly(int j, const SP& sp, const double* tw, cplx<T>* v) {
+  int jd, jm;
+  sp.divmod(j, jd, jm);
+  if (sp.ns() > 1) {
+    // twiddles W_n^{r (j mod ns) n/(ns R)}
+    cplx<T> w[R];
+    stage_twiddles_of<R, DIR, T>(tw, jm * sp.tstep(), w);
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+  }
+  dft<R, DIR>(v);
+  return jd * sp.ns() * R + jm;
+}
+
+template <int E, int R, int DIR, bool PAD, typename T, typename BufT, typename SP>
+PPE_HD void stage_write(BufT* buf, int es, int t, const SP& sp, const double* tw, cplx<T>* v) {
   constexpr int NB = E / R;
-  const int ns = f.ns[st];
-  const int span = ns * R;
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int j = t + f.tc * q;
-    int jd, jm;
-    fast_divmod(j, ns, f.inv_ns[st], jd, jm);
-    if (ns > 1) {
-      // twiddles W_n^{r (j mod ns) n/(ns R)}
-      cplx<T> w[R];
-      stage_twiddles_of<R, DIR, T>(tw, jm * f.tstep[st], w);
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], w[r]);
-    }
-    dft<R, DIR>(&v[q * R]);
-    const int base = jd * span + jm;
+    const int base = stage_butterfly<R, DIR, T>(t + sp.tc() * q, sp, tw, &v[q * R]);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       BufT o;
       o.re = v[q * R + r].re;
       o.im = v[q * R + r].im;
-      buf[lslot<PAD>(base + r * ns, es)] = o;
+      buf[lslot<PAD>(base + r * sp.ns(), es)] = o;
     }
   }
 }
 
 // The read half of stage 0 from a loader instead of LDS: v[q R + r] =
 // load(j + r n/R) for the thread's butterflies j = t + tc q.
-template <int E, int R, typename T, typename LoadF>
-PPE_HD void stage_load(int t, const FftDev& f, LoadF load, cplx<T>* v) {
+template <int E, int R, typename T, typename LoadF, typename SP>
+PPE_HD void stage_load(int t, const SP& sp, LoadF load, cplx<T>* v) {
   constexpr int NB = E / R;
-  const int nr = f.n / R;
+  const int nr = sp.n() / R;
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int j = t + f.tc * q;
+    const int j = t + sp.tc() * q;
 #pragma unroll
     for (int r = 0; r < R; ++r) v[q * R + r] = load(j + r * nr);
   }
@@ -279,33 +354,22 @@ PPE_HD void stage_load(int t, const FftDev& f, LoadF load, cplx<T>* v) {
 
 // The write half of a stage to a storer instead of LDS: store(n, x) for the
 // stage's outputs n (same twiddles and butterflies as stage_write).
-template <int E, int R, int DIR, typename T, typename StoreF>
-PPE_HD void stage_store(int t, int st, const FftDev& f, const double* tw, cplx<T>* v, StoreF store) {
+template <int E, int R, int DIR, typename T, typename StoreF, typename SP>
+PPE_HD void stage_store(int t, const SP& sp, const double* tw, cplx<T>* v, StoreF store) {
   constexpr int NB = E / R;
-  const int ns = f.ns[st];
-  const int span = ns * R;
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int j = t + f.tc * q;
-    int jd, jm;
-    fast_divmod(j, ns, f.inv_ns[st], jd, jm);
-    if (ns > 1) {
-      cplx<T> w[R];
-      stage_twiddles_of<R, DIR, T>(tw, jm * f.tstep[st], w);
+    const int base = stage_butterfly<R, DIR, T>(t + sp.tc() * q, sp, tw, &v[q * R]);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], w[r]);
-    }
-    dft<R, DIR>(&v[q * R]);
-    const int base = jd * span + jm;
-#pragma unroll
-    for (int r = 0; r < R; ++r) store(base + r * ns, v[q * R + r]);
+    for (int r = 0; r < R; ++r) store(base + r * sp.ns(), v[q * R + r]);
   }
 }
 
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
 // Copy the twiddle table of `f` into LDS (all threads of the block; the
 // caller's next barrier publishes it).
-__device__ __forceinline__ void stage_twiddles(double* lds_tw, const FftDev& f) {
+template <typename F>
+__device__ __forceinline__ void stage_twiddles(double* lds_tw, const F& f) {
   for (int q = threadIdx.x; q < 2 * f.n; q += blockDim.x) lds_tw[q] = f.tw[q];
 }
 
@@ -319,27 +383,27 @@ __device__ __forceinline__ void fft_lds(BufT* buf, int es, int t, bool active, c
     cplx<T> v[E];
     if (R == 8) {
       if constexpr (E % 8 == 0) {
-        if (active) stage_read<E, 8, PAD, T>(buf, es, t, f, v);
+        if (active) stage_read<E, 8, PAD, T>(buf, es, t, RtStage{f, s}, v);
         __syncthreads();
-        if (active) stage_write<E, 8, DIR, PAD, T>(buf, es, t, s, f, tw, v);
+        if (active) stage_write<E, 8, DIR, PAD, T>(buf, es, t, RtStage{f, s}, tw, v);
       }
     } else if (R == 4) {
       if constexpr (E % 4 == 0) {
-        if (active) stage_read<E, 4, PAD, T>(buf, es, t, f, v);
+        if (active) stage_read<E, 4, PAD, T>(buf, es, t, RtStage{f, s}, v);
         __syncthreads();
-        if (active) stage_write<E, 4, DIR, PAD, T>(buf, es, t, s, f, tw, v);
+        if (active) stage_write<E, 4, DIR, PAD, T>(buf, es, t, RtStage{f, s}, tw, v);
       }
     } else if (R == 3) {
       if constexpr (E % 3 == 0) {
-        if (active) stage_read<E, 3, PAD, T>(buf, es, t, f, v);
+        if (active) stage_read<E, 3, PAD, T>(buf, es, t, RtStage{f, s}, v);
         __syncthreads();
-        if (active) stage_write<E, 3, DIR, PAD, T>(buf, es, t, s, f, tw, v);
+        if (active) stage_write<E, 3, DIR, PAD, T>(buf, es, t, RtStage{f, s}, tw, v);
       }
     } else {
       if constexpr (E % 2 == 0) {
-        if (active) stage_read<E, 2, PAD, T>(buf, es, t, f, v);
+        if (active) stage_read<E, 2, PAD, T>(buf, es, t, RtStage{f, s}, v);
         __syncthreads();
-        if (active) stage_write<E, 2, DIR, PAD, T>(buf, es, t, s, f, tw, v);
+        if (active) stage_write<E, 2, DIR, PAD, T>(buf, es, t, RtStage{f, s}, tw, v);
       }
     }
     __syncthreads();
@@ -400,11 +464,11 @@ __device__ __forceinline__ void fft_io(BufT* buf, int es, int t, bool active, co
   {
     const int s = 0;
     PPE_FFT_IO_DISPATCH({
-      if (active) stage_load<E, R, T>(t, f, load, v);
+      if (active) stage_load<E, R, T>(t, RtStage{f, 0}, load, v);
       if (GSTORE && last == 0) {
-        if (active) stage_store<E, R, DIR, T>(t, 0, f, tw, v, store);
+        if (active) stage_store<E, R, DIR, T>(t, RtStage{f, 0}, tw, v, store);
       } else {
-        if (active) stage_write<E, R, DIR, PAD, T>(buf, es, t, 0, f, tw, v);
+        if (active) stage_write<E, R, DIR, PAD, T>(buf, es, t, RtStage{f, 0}, tw, v);
       }
     })
   }
@@ -412,17 +476,50 @@ __device__ __forceinline__ void fft_io(BufT* buf, int es, int t, bool active, co
   __syncthreads();
   for (int s = 1; s <= last; ++s) {
     PPE_FFT_IO_DISPATCH({
-      if (active) stage_read<E, R, PAD, T>(buf, es, t, f, v);
+      if (active) stage_read<E, R, PAD, T>(buf, es, t, RtStage{f, s}, v);
       if (GSTORE && s == last) {
-        if (active) stage_store<E, R, DIR, T>(t, s, f, tw, v, store);
+        if (active) stage_store<E, R, DIR, T>(t, RtStage{f, s}, tw, v, store);
       } else {
         __syncthreads();
-        if (active) stage_write<E, R, DIR, PAD, T>(buf, es, t, s, f, tw, v);
+        if (active) stage_write<E, R, DIR, PAD, T>(buf, es, t, RtStage{f, s}, tw, v);
         __syncthreads();
       }
     })
   }
 #undef PPE_FFT_IO_DISPATCH
+}
+
+// fft_io for a compile-time plan: the same stages and barriers, unrolled.
+template <int E, int DIR, bool PAD, bool GSTORE, typename T, int N, int S, typename BufT, typename LoadF,
+          typename StoreF>
+__device__ __forceinline__ void fft_io_ct_stage(BufT* buf, int es, int t, bool active, const double* tw,
+                                                LoadF& load, StoreF& store, cplx<T>* v) {
+  constexpr int R = CFft<N>::tab.radix[S];
+  constexpr int last = CFft<N>::nst - 1;
+  static_assert(E % R == 0, "E must be a multiple of every radix");
+  const CtStage<N, S> sp;
+  if constexpr (S == 0) {
+    if (active) stage_load<E, R, T>(t, sp, load, v);
+  } else {
+    if (active) stage_read<E, R, PAD, T>(buf, es, t, sp, v);
+  }
+  if constexpr (GSTORE && S == last) {
+    if (active) stage_store<E, R, DIR, T>(t, sp, tw, v, store);
+  } else {
+    if constexpr (S > 0) __syncthreads();
+    if (active) stage_write<E, R, DIR, PAD, T>(buf, es, t, sp, tw, v);
+    __syncthreads();
+  }
+  if constexpr (S < last)
+    fft_io_ct_stage<E, DIR, PAD, GSTORE, T, N, S + 1>(buf, es, t, active, tw, load, store, v);
+}
+
+template <int E, int DIR, bool PAD, bool GSTORE, typename T, int N, typename BufT, typename LoadF, typename StoreF>
+__device__ __forceinline__ void fft_io(BufT* buf, int es, int t, bool active, const CFft<N>&, const double* tw,
+                                       LoadF load, StoreF store) {
+  static_assert(E == CFft<N>::e, "elements per thread of the plan");
+  cplx<T> v[E];
+  fft_io_ct_stage<E, DIR, PAD, GSTORE, T, N, 0>(buf, es, t, active, tw, load, store, v);
 }
 #endif
 

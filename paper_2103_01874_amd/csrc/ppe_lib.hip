@@ -64,6 +64,7 @@ struct ppe_plan_s {
   int tx = 1;            // kx columns per block (z FFT)
   int txs = 1, pch = 1;  // systems per block, chunks per system (tri)
   int mc = 16;           // register rows per chunk (template of k_tri)
+  int fx_ct = 0, fz_ct = 0;  // power-of-two lengths run with compile-time FFT plans (0: run-time plan)
   int src_pt = 8;        // units per thread of k_source (2, 4 or 8)
   int src_vec = 2;       // cells per unit of k_source (1, or 2 when aligned)
   size_t lds_x = 0, lds_z = 0, lds_t = 0;
@@ -172,6 +173,12 @@ bool march_shape(const ppe_desc_t& d, int points, int max_txt, const char* env, 
 bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   const ppe_desc_t& d = p->d;
   if (!fft_factor(d.nx, p->fx) || !fft_factor(d.nz, p->fz)) return false;
+  {
+    const auto ct = [](int n) { return (n >= 16 && n <= 2048 && (n & (n - 1)) == 0) ? n : 0; };
+    const bool rt = tune_env("PPE_TUNE_RT_FFT") > 0;  // force the run-time plans
+    p->fx_ct = rt ? 0 : ct(d.nx);
+    p->fz_ct = rt ? 0 : ct(d.nz);
+  }
   Geom& g = p->g;
   g.nx = d.nx;
   g.ny = d.ny;
@@ -331,6 +338,31 @@ Work<TS> make_work(ppe_plan_s* p, int inst0) {
     default: return PPE_ERR_UNSUPPORTED;            \
   }
 
+// Launch CALL with FV the kernels' FFT plan of the host plan HF and E its
+// elements per thread: a compile-time CFft<N> when CT (the plan's
+// power-of-two length, 16..2048), else the run-time plan.
+#define PPE_FFT_CT_CASE(NN, HF, FV, CALL) \
+  case NN: {                              \
+    constexpr int E = CFft<NN>::e;        \
+    const CFft<NN> FV{(HF).tw};           \
+    CALL;                                 \
+  } break;
+#define PPE_FFT_SWITCH(CT, HF, FV, CALL)                                              \
+  switch (CT) {                                                                     \
+    PPE_FFT_CT_CASE(16, HF, FV, CALL)                                               \
+    PPE_FFT_CT_CASE(32, HF, FV, CALL)                                               \
+    PPE_FFT_CT_CASE(64, HF, FV, CALL)                                               \
+    PPE_FFT_CT_CASE(128, HF, FV, CALL)                                              \
+    PPE_FFT_CT_CASE(256, HF, FV, CALL)                                              \
+    PPE_FFT_CT_CASE(512, HF, FV, CALL)                                              \
+    PPE_FFT_CT_CASE(1024, HF, FV, CALL)                                             \
+    PPE_FFT_CT_CASE(2048, HF, FV, CALL)                                             \
+    default: {                                                                      \
+      const FftDev FV = to_dev(HF);                                                 \
+      PPE_E_SWITCH(FV.e, CALL);                                                     \
+    } break;                                                                        \
+  }
+
 hipEvent_t prof_event(ppe_plan_s* p) {
   if (!p->pool.empty()) {
     hipEvent_t e = p->pool.back();
@@ -388,13 +420,14 @@ ppe_status_t launch_fft_z(ppe_plan_s* p, const Work<TS>& W, int nb, int dir, int
   const Geom& g = p->g;
   dim3 grid(g.ny, (g.hx + p->tx - 1) / p->tx, nb);
   dim3 block(p->tx * p->fz.tc);
-  FftDev fz = to_dev(p->fz);
   if (dir < 0) {
     PPE_TIMED(p, "k_fft_z_fwd",
-              PPE_E_SWITCH(fz.e, (k_fft_z<TS, E, -1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check))));
+              PPE_FFT_SWITCH(p->fz_ct, p->fz, fz,
+                             (k_fft_z<TS, E, -1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check))));
   } else {
     PPE_TIMED(p, "k_fft_z_inv",
-              PPE_E_SWITCH(fz.e, (k_fft_z<TS, E, +1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check))));
+              PPE_FFT_SWITCH(p->fz_ct, p->fz, fz,
+                             (k_fft_z<TS, E, +1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check))));
   }
   return PPE_OK;
 }
@@ -447,18 +480,17 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   const long long npairs = (nrows + 1) / 2;
   dim3 xgrid((unsigned)((npairs + p->rp - 1) / p->rp), 1, nb);
   dim3 xblock(p->rp * p->fx.tc);
-  FftDev fx = to_dev(p->fx);
   PPE_TIMED(p, "k_rhs",
             PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT, true><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads, march_lds(p->mrhs, 2),
                                                         p->stream>>>(tab, g, p->mrhs.m, W))));
   // the right-hand-side sums are reduced by block 0 of the first row FFT
   PPE_TIMED(p, "k_r2c",
-            PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
+            PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
                                    tab, g, fx, W, p->b64, p->rp, 0, FinishArgs{p->mrhs.grid, tol}))));
   ppe_status_t st = launch_chain<TS>(p, W, nb, 0);
   if (st != PPE_OK) return st;
   PPE_TIMED(p, "k_c2r",
-            PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 0, 0))));
+            PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 0, 0))));
   if (mixed) {
     for (int it = 0; it < p->d.max_refine; ++it) {
       PPE_TIMED(p, "k_resid",
@@ -467,12 +499,12 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
                                                                                                     p->r64))));
       finish(p, tab, inst0, nb, p->mres.grid, FIN_RESID, 1);
       PPE_TIMED(p, "k_r2c",
-                PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
+                PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
                                        tab, g, fx, W, p->r64, p->rp, 1, FinishArgs{0, 0.0}))));
       st = launch_chain<TS>(p, W, nb, 1);
       if (st != PPE_OK) return st;
       PPE_TIMED(p, "k_c2r",
-                PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1))));
+                PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1))));
     }
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
@@ -492,7 +524,6 @@ ppe_status_t varcoef_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb
   const long long npairs = (nrows + 1) / 2;
   dim3 xgrid((unsigned)((npairs + p->rp - 1) / p->rp), 1, nb);
   dim3 xblock(p->rp * p->fx.tc);
-  FftDev fx = to_dev(p->fx);
   PPE_TIMED(p, "k_rhs",
             PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT, false><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads,
                                                                march_lds(p->mrhs, 1), p->stream>>>(tab, g,
@@ -539,12 +570,12 @@ ppe_status_t varcoef_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb
            h0 ? h0 + it : nullptr, hs);
     if (it == max_iters) break;
     PPE_TIMED(p, "k_r2c",
-              PPE_E_SWITCH(fx.e, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
+              PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
                                      tab, g, fx, W, p->r64, p->rp, 1, FinishArgs{0, 0.0}))));
     ppe_status_t st = launch_chain<TS>(p, W, nb, 1);
     if (st != PPE_OK) return st;
     PPE_TIMED(p, "k_c2r",
-              PPE_E_SWITCH(fx.e, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1))));
+              PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1))));
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
 }
@@ -560,10 +591,10 @@ bool ptrs_ok(const void* const* a, int n) {
 
 namespace {
 // Dynamic LDS above 64 KiB must be enabled per kernel (all z-FFT variants).
-template <typename TS, int E>
+template <typename TS, int E, typename F = FftDev>
 hipError_t allow_big_lds_e(int bytes) {
-  const void* fns[] = {reinterpret_cast<const void*>(&k_fft_z<TS, E, -1>),
-                       reinterpret_cast<const void*>(&k_fft_z<TS, E, +1>)};
+  const void* fns[] = {reinterpret_cast<const void*>(&k_fft_z<TS, E, -1, F>),
+                       reinterpret_cast<const void*>(&k_fft_z<TS, E, +1, F>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -580,6 +611,14 @@ hipError_t allow_big_lds_t(int bytes) {
   if (e == hipSuccess) e = allow_big_lds_e<TS, 6>(bytes);
   if (e == hipSuccess) e = allow_big_lds_e<TS, 8>(bytes);
   if (e == hipSuccess) e = allow_big_lds_e<TS, 12>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<16>::e, CFft<16>>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<32>::e, CFft<32>>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<64>::e, CFft<64>>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<128>::e, CFft<128>>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<256>::e, CFft<256>>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<512>::e, CFft<512>>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<1024>::e, CFft<1024>>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<2048>::e, CFft<2048>>(bytes);
   return e;
 }
 hipError_t allow_big_lds(int bytes) {

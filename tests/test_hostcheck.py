@@ -25,6 +25,8 @@ def hc():
     lib.hc_tri.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp]
     lib.hc_fft_plan.argtypes = [ctypes.c_int, ip, ip, ip, ip]
     lib.hc_twiddles.argtypes = [ctypes.c_int, dp]
+    lib.hc_fft_ct.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+    lib.hc_ct_plan_check.argtypes = [ctypes.c_int]
     return lib
 
 
@@ -47,6 +49,24 @@ def test_fft_stages_match_numpy(hc, n):
     assert hc.hc_fft(n, +1, _p(xin), _p(out)) == 0
     y = out[0::2] + 1j * out[1::2]
     assert np.abs(y - n * np.fft.ifft(x)).max() < 1e-14 * np.abs(x).sum() + 1e-15
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048])
+def test_compile_time_plans_equal_the_host_plans(hc, n):
+    """Power-of-two lengths run with compile-time stage tables: the same
+    stages as the host factorisation, and bit for bit the same transform."""
+    assert hc.hc_ct_plan_check(n) == 0
+    rng = np.random.default_rng(100 + n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    xin = np.ascontiguousarray(np.stack([x.real, x.imag], -1).ravel())
+    for d in (-1, +1):
+        a, b = np.zeros(2 * n), np.zeros(2 * n)
+        assert hc.hc_fft(n, d, _p(xin), _p(a)) == 0
+        assert hc.hc_fft_ct(n, d, _p(xin), _p(b)) == 0
+        assert np.array_equal(a, b)
+    y = b[0::2] + 1j * b[1::2]
+    assert np.abs(y - n * np.fft.ifft(x)).max() < 1e-14 * np.abs(x).sum() + 1e-15
+    assert hc.hc_fft_ct(48, -1, _p(xin), _p(b)) != 0 and hc.hc_ct_plan_check(48) != 0
 
 
 def test_fft_rejects_other_primes(hc):
