@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace ppe {
 
 #define PPE_HD __host__ __device__ __forceinline__
@@ -490,7 +492,9 @@ __device__ __forceinline__ void fft_io(BufT* buf, int es, int t, bool active, co
 }
 
 // fft_io for a compile-time plan: the same stages and barriers, unrolled.
-template <int E, int DIR, bool PAD, bool GSTORE, typename T, int N, int S, typename BufT, typename LoadF,
+// PRE: load(v) fills the thread's stage-0 inputs v[q R + r] = x(j + r n/R),
+// j = t + tc q, all at once (instead of one call per element).
+template <int E, int DIR, bool PAD, bool GSTORE, bool PRE, typename T, int N, int S, typename BufT, typename LoadF,
           typename StoreF>
 __device__ __forceinline__ void fft_io_ct_stage(BufT* buf, int es, int t, bool active, const double* tw,
                                                 LoadF& load, StoreF& store, cplx<T>* v) {
@@ -499,7 +503,11 @@ __device__ __forceinline__ void fft_io_ct_stage(BufT* buf, int es, int t, bool a
   static_assert(E % R == 0, "E must be a multiple of every radix");
   const CtStage<N, S> sp;
   if constexpr (S == 0) {
-    if (active) stage_load<E, R, T>(t, sp, load, v);
+    if constexpr (PRE) {
+      if (active) load(v);
+    } else {
+      if (active) stage_load<E, R, T>(t, sp, load, v);
+    }
   } else {
     if (active) stage_read<E, R, PAD, T>(buf, es, t, sp, v);
   }
@@ -511,7 +519,7 @@ __device__ __forceinline__ void fft_io_ct_stage(BufT* buf, int es, int t, bool a
     __syncthreads();
   }
   if constexpr (S < last)
-    fft_io_ct_stage<E, DIR, PAD, GSTORE, T, N, S + 1>(buf, es, t, active, tw, load, store, v);
+    fft_io_ct_stage<E, DIR, PAD, GSTORE, PRE, T, N, S + 1>(buf, es, t, active, tw, load, store, v);
 }
 
 template <int E, int DIR, bool PAD, bool GSTORE, typename T, int N, typename BufT, typename LoadF, typename StoreF>
@@ -519,8 +527,22 @@ __device__ __forceinline__ void fft_io(BufT* buf, int es, int t, bool active, co
                                        LoadF load, StoreF store) {
   static_assert(E == CFft<N>::e, "elements per thread of the plan");
   cplx<T> v[E];
-  fft_io_ct_stage<E, DIR, PAD, GSTORE, T, N, 0>(buf, es, t, active, tw, load, store, v);
+  fft_io_ct_stage<E, DIR, PAD, GSTORE, false, T, N, 0>(buf, es, t, active, tw, load, store, v);
 }
+
+// fft_io with a whole-thread stage-0 loader (see fft_io_ct_stage's PRE).
+template <int E, int DIR, bool PAD, bool GSTORE, typename T, int N, typename BufT, typename LoadV, typename StoreF>
+__device__ __forceinline__ void fft_io_v(BufT* buf, int es, int t, bool active, const CFft<N>&, const double* tw,
+                                         LoadV loadv, StoreF store) {
+  static_assert(E == CFft<N>::e, "elements per thread of the plan");
+  cplx<T> v[E];
+  fft_io_ct_stage<E, DIR, PAD, GSTORE, true, T, N, 0>(buf, es, t, active, tw, loadv, store, v);
+}
+
+template <typename F>
+struct is_ct_fft : std::false_type {};
+template <int N>
+struct is_ct_fft<CFft<N>> : std::true_type {};
 #endif
 
 // ---------------------------------------------------------------------------

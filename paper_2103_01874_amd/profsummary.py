@@ -32,7 +32,8 @@ def family(name: str) -> str:
     """Kernel family as the library's event timing names it."""
     n = _short(name)
     if n.startswith("k_fft_z"):
-        return "k_fft_z_fwd" if ", -1>" in n else "k_fft_z_inv"
+        # k_fft_z<TS, E, DIR[, plan]>: DIR = -1 forward, 1 inverse
+        return "k_fft_z_fwd" if re.match(r"k_fft_z<[^,]+, *\d+, *-1\b", n) else "k_fft_z_inv"
     return re.sub(r"<.*", "", n)
 
 
