@@ -111,6 +111,38 @@ def test_fp64_sheet_256x128x256_full_oracle():
     check(pr, got, rec, oracle_step(pr, ))
 
 
+# x and z lengths 512..2048 run the compile-time FFT plans: at 512 a row
+# transform fills one wavefront (the inverse real FFT takes the mirror half of
+# the spectrum from a partner lane across all 64 lanes); above it a transform
+# spans several wavefronts and reads the mirror half itself.  z lengths above
+# 1024 do not fit the column kernel's LDS and are rejected by the plan.
+LARGE_POW2 = [(512, 4, 16), (1024, 2, 16), (2048, 2, 8), (16, 4, 512), (16, 2, 1024), (512, 3, 512)]
+
+
+@pytest.mark.parametrize("ybc", [0, 1])
+@pytest.mark.parametrize("precision", [binding.PPE_PREC_FP64, binding.PPE_PREC_MIXED])
+@pytest.mark.parametrize("shape", LARGE_POW2)
+def test_large_power_of_two_lengths(shape, precision, ybc):
+    pr = synth.random_problem(*shape, seed=7 + sum(shape) + ybc, ybc=ybc)
+    (got,), (rec,) = gpu_step([pr], precision=precision)
+    check(pr, got, rec, oracle_step(pr))
+
+
+def test_sheet_512x256x512_full_oracle_fp64_and_mixed():
+    """The 512x256x512 sheet (rho 640/60, five interface modes) in the two
+    launch configurations the benchmark times for it: the FP64 direct solve,
+    and FP32 spectra with one FP64 refinement sweep.  Both against one FP64
+    oracle solve, every point."""
+    pr = synth.sheet_512()
+    ref = oracle_step(pr)
+    (got,), (rec,) = gpu_step([pr])
+    check(pr, got, rec, ref)
+    del got
+    (got,), (rec,) = gpu_step([pr], precision=binding.PPE_PREC_MIXED, max_refine=1)
+    check(pr, got, rec, ref)
+    assert rec["iters"] <= 1
+
+
 @pytest.mark.parametrize("shape", [(32, 32, 32), (64, 32, 48), (96, 64, 96)])
 def test_mixed_refined_sheet(shape):
     pr = synth.sheet_problem(*shape, seed=11, rho_l=640.0, rho_g=60.0, nmodes=5)
