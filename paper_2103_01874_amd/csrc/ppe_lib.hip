@@ -237,7 +237,7 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   // z-marching stencils: TXT x TJ tiles (TXT a divisor of nx, <= 128), KC planes
   // per chunk; the tile height per kernel trades halo traffic against registers
   if (!march_shape(d, 256, 64, "PPE_TUNE_TJ_RHS", p->mrhs) || !march_shape(d, 256, 64, "PPE_TUNE_TJ_COR", p->mcor) ||
-      !march_shape(d, 512, 128, "PPE_TUNE_TJ_RES", p->mres))
+      !march_shape(d, 256, 64, "PPE_TUNE_TJ_RES", p->mres))
     return false;
   if ((size_t)3 * p->mcor.tslots * 8 > 65536) return false;
   // per-instance partial-sum stride: the largest grid.x of a reducing kernel
