@@ -77,30 +77,46 @@ def source_hash() -> str:
 
 
 def algorithmic_bytes(kernel: str, nx: int, ny: int, nz: int, precision: int, mode_update: bool = False,
-                      n_iface: int = 0) -> float:
+                      n_iface: int = 0, ctx: dict | None = None) -> float:
     """Bytes one launch must move for one instance (the compulsory traffic).
 
     N cells, Nv = nx (ny+1) nz v-faces, Ns = (nx/2+1) ny nz spectral values of
     cs bytes (16 FP64, 8 FP32); n_iface interface cells (0 < C < 1) for the
-    target-divergence pass."""
+    target-divergence pass.  `ctx` says how the workload launches a kernel:
+    split (k_rhs with the p_hat term; False in the Eq. (25) iteration, which
+    assembles only c), p_aliased (k_correct given one array for p, p^n and
+    p^{n-1}), first_frac (the share of k_resid_var launches that form p_0 from
+    p^n, p^{n-1}), viscous_separate (predictor given its own viscous-term
+    velocities)."""
+    ctx = ctx or {}
     N = nx * ny * nz
     Nv = nx * (ny + 1) * nz
     Ns = (nx // 2 + 1) * ny * nz
     cs = 16 if precision == 0 else 8
+    split = ctx.get("split", True)
+    first = ctx.get("first_frac", 0.0)
+    pred_in = 8 * (8 * N + Nv) + (8 * (2 * N + Nv) if ctx.get("viscous_separate", False) else 0)
     table = {
-        "k_rhs": 8 * (6 * N + Nv) + 8 * N,           # u*, v*, w*, rho, p^n, p^{n-1}, S -> b
+        # u*, v*, w*, rho, p^n, p^{n-1}, S -> b; without the split term u*, v*, w*, S -> c
+        "k_rhs": (8 * (6 * N + Nv) if split else 8 * (3 * N + Nv)) + 8 * N,
         "k_r2c": 8 * N + cs * Ns,                      # b (or r) -> half spectrum
         "k_fft_z_fwd": 2 * cs * Ns,
         "k_fft_z_inv": 2 * cs * Ns,
         "k_tri": 2 * cs * Ns,
         "k_c2r": cs * Ns + 8 * N + (8 * N if mode_update else 0),
         "k_resid": 3 * 8 * N,                          # b, p -> r
-        "k_correct": 8 * (7 * N + Nv) + 8 * (2 * N + Nv),  # u*,v*,w*,rho,p^n,p^{n-1},p,S -> u,v,w
+        # c, rho, p -> r; the first sweep reads p^n, p^{n-1} instead of p and also writes p
+        "k_resid_var": (1 - first) * 32 * N + first * 48 * N,
+        # u*,v*,w*,rho,p^n,p^{n-1},p,S -> u,v,w (one pressure array when aliased)
+        "k_correct": 8 * ((5 if ctx.get("p_aliased", False) else 7) * N + Nv) + 8 * (2 * N + Nv),
         # C and one phase divergence -> S everywhere; interface cells also read
         # the other divergence, m', A/V0, rho_g, rho_l (8 B each) and the mask (1 B)
         "k_source": 24 * N + 41 * n_iface,
-        # u^n, v^n, w^n, rho^n, rho^{n+1}, mu, C, sigma, kappa -> u^p, v^p, w^p
-        "k_predict": 8 * (8 * N + Nv) + 8 * (2 * N + Nv),
+        # each component reads u^n, v^n, w^n, rho^n, rho^{n+1}, mu, C, sigma,
+        # kappa (and the viscous-term velocities if separate), writes its own
+        "k_predict_u": pred_in + 8 * N,
+        "k_predict_v": pred_in + 8 * Nv,
+        "k_predict_w": pred_in + 8 * N,
     }
     return float(table.get(kernel, 0.0))
 
@@ -402,21 +418,30 @@ def main():
         plan.profile(False)
         dom = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
         kname, kv = dom
-        per_launch = algorithmic_bytes(kname, pr.nx, pr.ny, pr.nz, precision,
-                                       mode_update=(kname == "k_c2r" and max_refine > 0), n_iface=n_iface)
-        if kname == "k_c2r" and max_refine > 0:
-            # half of the launches update p (read + write), half write it: average
-            per_launch = 0.5 * (algorithmic_bytes(kname, pr.nx, pr.ny, pr.nz, precision, False)
-                                + algorithmic_bytes(kname, pr.nx, pr.ny, pr.nz, precision, True))
+        varcoef = args.workload.startswith("varcoef")
+        ctx = {"split": not varcoef, "p_aliased": varcoef,
+               "first_frac": 1.0 / (rec["iters"] + 1) if varcoef else 0.0}
+
+        def launch_bytes(k):
+            if k == "k_c2r" and varcoef:  # every sweep updates p
+                return algorithmic_bytes(k, pr.nx, pr.ny, pr.nz, precision, True, ctx=ctx)
+            if k == "k_c2r" and max_refine > 0:
+                # one launch writes p, the refinement launches update it: average
+                nu = min(max_refine, rec["iters"])
+                return (algorithmic_bytes(k, pr.nx, pr.ny, pr.nz, precision, False, ctx=ctx)
+                        + nu * algorithmic_bytes(k, pr.nx, pr.ny, pr.nz, precision, True, ctx=ctx)) / (1 + nu)
+            return algorithmic_bytes(k, pr.nx, pr.ny, pr.nz, precision, n_iface=n_iface, ctx=ctx)
+
+        per_launch = launch_bytes(kname)
         achieved = per_launch / (kv["avg_us"] * 1e-6) / 1e9
         traffic = counter_traffic(args.workload, kname)
         roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kname,
                     "avg_launch_us": kv["avg_us"], "bytes_per_launch": per_launch}
-        # every kernel's algorithmic rate, for the per-kernel view (k_c2r: mode 0 figure)
+        # every kernel's algorithmic rate, for the per-kernel view
         kernels_gbs = {}
         for k, v in kernels.items():
-            bpl = algorithmic_bytes(k, pr.nx, pr.ny, pr.nz, precision, n_iface=n_iface)
+            bpl = launch_bytes(k)
             if bpl > 0:
                 kernels_gbs[k] = round(bpl / (v["avg_us"] * 1e-6) / 1e9, 1)
         roofline["kernels_gbs"] = kernels_gbs
