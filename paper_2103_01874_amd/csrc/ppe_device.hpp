@@ -340,6 +340,15 @@ PPE_HD void stage_write(BufT* buf, int es, int t, const SP& sp, const double* tw
   }
 }
 
+// Twiddles and butterflies of all the thread's groups, in place: after the
+// last stage v[q R + r] is output j + r n/R of the transform, j = t + tc q.
+template <int E, int R, int DIR, typename T, typename SP>
+PPE_HD void stage_bfly_all(int t, const SP& sp, const double* tw, cplx<T>* v) {
+  constexpr int NB = E / R;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) stage_butterfly<R, DIR, T>(t + sp.tc() * q, sp, tw, &v[q * R]);
+}
+
 // The read half of stage 0 from a loader instead of LDS: v[q R + r] =
 // load(j + r n/R) for the thread's butterflies j = t + tc q.
 template <int E, int R, typename T, typename LoadF, typename SP>
@@ -494,13 +503,16 @@ __device__ __forceinline__ void fft_io(BufT* buf, int es, int t, bool active, co
 // fft_io for a compile-time plan: the same stages and barriers, unrolled.
 // PRE: load(v) fills the thread's stage-0 inputs v[q R + r] = x(j + r n/R),
 // j = t + tc q, all at once (instead of one call per element).
+// POST (with GSTORE): the last stage's butterflies run in registers and
+// store(v) receives all of the thread's outputs at once (see stage_bfly_all).
 template <int E, int DIR, bool PAD, bool GSTORE, bool PRE, typename T, int N, int S, typename BufT, typename LoadF,
-          typename StoreF>
+          typename StoreF, bool POST = false>
 __device__ __forceinline__ void fft_io_ct_stage(BufT* buf, int es, int t, bool active, const double* tw,
                                                 LoadF& load, StoreF& store, cplx<T>* v) {
   constexpr int R = CFft<N>::tab.radix[S];
   constexpr int last = CFft<N>::nst - 1;
   static_assert(E % R == 0, "E must be a multiple of every radix");
+  static_assert(!POST || GSTORE, "POST hands the outputs to the storer");
   const CtStage<N, S> sp;
   if constexpr (S == 0) {
     if constexpr (PRE) {
@@ -512,14 +524,22 @@ __device__ __forceinline__ void fft_io_ct_stage(BufT* buf, int es, int t, bool a
     if (active) stage_read<E, R, PAD, T>(buf, es, t, sp, v);
   }
   if constexpr (GSTORE && S == last) {
-    if (active) stage_store<E, R, DIR, T>(t, sp, tw, v, store);
+    if constexpr (POST) {
+      if (active) {
+        stage_bfly_all<E, R, DIR, T>(t, sp, tw, v);
+        store(v);
+      }
+    } else {
+      if (active) stage_store<E, R, DIR, T>(t, sp, tw, v, store);
+    }
   } else {
     if constexpr (S > 0) __syncthreads();
     if (active) stage_write<E, R, DIR, PAD, T>(buf, es, t, sp, tw, v);
     __syncthreads();
   }
   if constexpr (S < last)
-    fft_io_ct_stage<E, DIR, PAD, GSTORE, PRE, T, N, S + 1>(buf, es, t, active, tw, load, store, v);
+    fft_io_ct_stage<E, DIR, PAD, GSTORE, PRE, T, N, S + 1, BufT, LoadF, StoreF, POST>(buf, es, t, active, tw, load,
+                                                                                      store, v);
 }
 
 template <int E, int DIR, bool PAD, bool GSTORE, typename T, int N, typename BufT, typename LoadF, typename StoreF>
@@ -537,6 +557,17 @@ __device__ __forceinline__ void fft_io_v(BufT* buf, int es, int t, bool active, 
   static_assert(E == CFft<N>::e, "elements per thread of the plan");
   cplx<T> v[E];
   fft_io_ct_stage<E, DIR, PAD, GSTORE, true, T, N, 0>(buf, es, t, active, tw, loadv, store, v);
+}
+
+// fft_io whose last stage hands all of the thread's outputs to store(v):
+// v[q R + r] is output t + tc q + r n/R, R the last radix.
+template <int E, int DIR, bool PAD, typename T, int N, typename BufT, typename LoadF, typename StoreV>
+__device__ __forceinline__ void fft_io_post(BufT* buf, int es, int t, bool active, const CFft<N>&, const double* tw,
+                                            LoadF load, StoreV storev) {
+  static_assert(E == CFft<N>::e, "elements per thread of the plan");
+  cplx<T> v[E];
+  fft_io_ct_stage<E, DIR, PAD, true, false, T, N, 0, BufT, LoadF, StoreV, true>(buf, es, t, active, tw, load, storev,
+                                                                               v);
 }
 
 template <typename F>
