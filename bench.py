@@ -121,6 +121,24 @@ def algorithmic_bytes(kernel: str, nx: int, ny: int, nz: int, precision: int, mo
     return float(table.get(kernel, 0.0))
 
 
+def copy_gbs(dev, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Rate of a plain device-to-device copy of nbytes (read + write bytes / time)."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(pr, budget_s: float = 12.0):
     """The FP64 oracle on the same workload, timed on the host."""
     import oracle as O
@@ -445,6 +463,10 @@ def main():
             if bpl > 0:
                 kernels_gbs[k] = round(bpl / (v["avg_us"] * 1e-6) / 1e9, 1)
         roofline["kernels_gbs"] = kernels_gbs
+        # the same box's plain device copy, for scale next to the vendor peak
+        cg = copy_gbs(dev)
+        roofline["copy_gbs"] = round(cg, 1)
+        roofline["frac_of_copy"] = achieved / cg
         kernels = {k: round(v["avg_us"], 2) for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms"])}
 
     if args.copy_bytes > 0:
