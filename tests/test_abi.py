@@ -83,3 +83,11 @@ def test_workspace_accounts_for_precision_and_batch(lib):
     assert b > 3 * a
     # mixed: FP32 spectrum plus the FP64 refinement residual buffer
     assert m - a == spec32 - spec64 + 64 * 32 * 64 * 8
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No CPU fallback: without the built library every entry point raises."""
+    from paper_2103_01874_amd import binding
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(binding.PPEError, match="not built"):
+        binding.load(str(tmp_path / "libppe.so"))
