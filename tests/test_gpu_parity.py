@@ -112,11 +112,14 @@ def test_fp64_sheet_256x128x256_full_oracle():
 
 
 # x and z lengths 512..2048 run the compile-time FFT plans: at 512 a row
-# transform fills one wavefront (the inverse real FFT takes the mirror half of
-# the spectrum from a partner lane across all 64 lanes); above it a transform
-# spans several wavefronts and reads the mirror half itself.  z lengths above
-# 1024 do not fit the column kernel's LDS and are rejected by the plan.
-LARGE_POW2 = [(512, 4, 16), (1024, 2, 16), (2048, 2, 8), (16, 4, 512), (16, 2, 1024), (512, 3, 512)]
+# transform fills one wavefront (the real FFTs exchange the mirror half of
+# the spectrum with a partner lane across all 64 lanes); above it a transform
+# spans several wavefronts and the mirror half goes through LDS or a second
+# read.  z lengths above 1024 leave the column kernel fewer kx columns per
+# block (4 at 1152..2048), so that a column still fits the LDS of a CU; 1152
+# and 1536 run the run-time plan (radix 3).
+LARGE_POW2 = [(512, 4, 16), (1024, 2, 16), (2048, 2, 8), (16, 4, 512), (16, 2, 1024), (512, 3, 512),
+              (8, 2, 2048), (8, 3, 1536), (16, 2, 1152)]
 
 
 @pytest.mark.parametrize("ybc", [0, 1])
@@ -124,7 +127,13 @@ LARGE_POW2 = [(512, 4, 16), (1024, 2, 16), (2048, 2, 8), (16, 4, 512), (16, 2, 1
 @pytest.mark.parametrize("shape", LARGE_POW2)
 def test_large_power_of_two_lengths(shape, precision, ybc):
     pr = synth.random_problem(*shape, seed=7 + sum(shape) + ybc, ybc=ybc)
-    (got,), (rec,) = gpu_step([pr], precision=precision)
+    # The refinement stops on the divergence residual; the pressure error can
+    # exceed it by the conditioning of the solve, which FP32 spectra of long
+    # transforms expose (16x2x1152, outflow: one sweep reaches eps_div 6.9e-13
+    # and eps_p 1.1e-12).  The mixed runs therefore ask for 1e-13, so that p
+    # meets the 1e-12 parity bound too.
+    tol = 1e-12 if precision == binding.PPE_PREC_FP64 else 1e-13
+    (got,), (rec,) = gpu_step([pr], precision=precision, tol=tol, max_refine=3)
     check(pr, got, rec, oracle_step(pr))
 
 
