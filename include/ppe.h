@@ -86,6 +86,17 @@ typedef enum {
 #define PPE_FLAG_VARCOEF 1   /* also allocate the FP64 residual buffer that
                                 ppe_solve_varcoef needs (always present for
                                 PPE_PREC_MIXED): 8 bytes per cell and instance */
+#define PPE_FLAG_Y_REFINE 2  /* follow every y tridiagonal solve of a system
+                                whose smallest eigenvalue is below about 1e-2
+                                (s + the lowest y mode, Sec. 5.4 scaling) by
+                                one correction solve of its residual, formed in
+                                difference form: restores ~1e-15 on systems the
+                                elimination alone leaves at ~4 eps / (that
+                                eigenvalue).  Always on for ny > 256; the flag
+                                asks for it at any ny (wide domains with smooth
+                                sources: s = (dy k)^2 falls below 1e-5 when the
+                                horizontal extent exceeds ~2000 dy).  Costs a
+                                second tridiagonal launch over those systems. */
 
 /* Precision of the spectral passes (FFTs and tridiagonal sweeps). */
 typedef enum {

@@ -22,6 +22,7 @@ PPE_PREC_MIXED = 1
 PPE_YBC_WALLS = 0
 PPE_YBC_OUTFLOW = 1
 PPE_FLAG_VARCOEF = 1
+PPE_FLAG_Y_REFINE = 2
 PPE_OK = 0
 PPE_ERR_ARG = -1
 PPE_ERR_NOT_CONVERGED = -4

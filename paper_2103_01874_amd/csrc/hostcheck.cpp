@@ -234,6 +234,37 @@ int hc_ct_plan_check(int n) {
   }
 }
 
+// One solve followed by one refinement step whose residual is formed in
+// difference form, (x_{j+1} - x_j) - (x_j - x_{j-1}) - s x_j: for a smooth x
+// the differences are small and nearly exact, where x_{j-1} - (2+s) x_j +
+// x_{j+1} cancels.  Regular systems only (flags bit 1: outflow top).
+int hc_tri_refined(int ny, int P, double s, int flags, const double* rhs, double* x) {
+  if (P < 1 || ny < 2 * P || (flags & 1)) return -1;
+  const int outflow = (flags >> 1) & 1;
+  const int mmax = (ny + P - 1) / P;
+  auto pass = [&](const double* r, double* y) {
+    if (mmax <= 4) run_tri<4>(ny, P, s, 0, outflow, r, y);
+    else if (mmax <= 8) run_tri<8>(ny, P, s, 0, outflow, r, y);
+    else if (mmax <= 16) run_tri<16>(ny, P, s, 0, outflow, r, y);
+  };
+  if (mmax > 16) return -1;
+  pass(rhs, x);
+  std::vector<double> res(2 * (size_t)ny), d(2 * (size_t)ny);
+  for (int c = 0; c < 2; ++c) {
+    for (int j = 0; j < ny; ++j) {
+      const double xj = x[2 * j + c];
+      const double up = j + 1 < ny ? x[2 * (j + 1) + c] - xj : 0.0;
+      const double dn = j > 0 ? xj - x[2 * (j - 1) + c] : 0.0;
+      double ax = up - dn - s * xj;
+      if (j == ny - 1 && outflow) ax -= 2.0 * xj;
+      res[2 * j + c] = rhs[2 * j + c] - ax;
+    }
+  }
+  pass(res.data(), d.data());
+  for (int q = 0; q < 2 * ny; ++q) x[q] += d[q];
+  return 0;
+}
+
 // One y system: x_{j-1} + beta_j x_j + x_{j+1} = rhs_j (scaled form, complex
 // interleaved), P chunks.  flags bit 0: apply the pin and the mean removal of
 // the singular (0,0) system; bit 1: outflow top row (beta_{ny-1} = -3 - s).

@@ -65,6 +65,7 @@ struct ppe_plan_s {
   int txs = 1, pch = 1;  // systems per block, chunks per system (tri)
   int mc = 16;           // register rows per chunk (template of k_tri)
   int fx_ct = 0, fz_ct = 0;  // power-of-two lengths run with compile-time FFT plans (0: run-time plan)
+  bool tri_refine = false;  // one difference-form refinement step in the y solve
   int src_pt = 8;        // units per thread of k_source (2, 4 or 8)
   int src_vec = 2;       // cells per unit of k_source (1, or 2 when aligned)
   size_t lds_x = 0, lds_z = 0, lds_t = 0;
@@ -119,7 +120,7 @@ bool desc_ok(const ppe_desc_t* d) {
   if (!(d->lx > 0) || !(d->ly > 0) || !(d->lz > 0)) return false;
   if (d->precision != PPE_PREC_FP64 && d->precision != PPE_PREC_MIXED) return false;
   if (d->ybc != PPE_YBC_WALLS && d->ybc != PPE_YBC_OUTFLOW) return false;
-  if ((d->flags & ~PPE_FLAG_VARCOEF) != 0 || d->reserved != 0) return false;
+  if ((d->flags & ~(PPE_FLAG_VARCOEF | PPE_FLAG_Y_REFINE)) != 0 || d->reserved != 0) return false;
   if (d->batch < 1 || d->batch > PPE_MAX_BATCH) return false;
   if (d->max_refine < 0 || d->max_refine > 64) return false;
   if (!(d->tol >= 0)) return false;
@@ -227,6 +228,12 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   if (p->txs * P > 256) return false;
   const int mmax = (d.ny + P - 1) / P;
   p->mc = mmax <= 4 ? 4 : (mmax <= 8 ? 8 : 16);
+  // The elimination leaves about 4 eps / lambda_min relative error on a system
+  // whose smallest eigenvalue is lambda_min (s for zero-flux ends, s +
+  // 4 sin^2(pi / 4 ny) with the outflow top, 4 sin^2(pi / 2 ny) for the pinned
+  // zero mode).  Above 256 rows the last two reach 1e-12 in the pressure of
+  // ordinary fields; one refinement step of the y solve restores them.
+  p->tri_refine = d.ny > 256 || (d.flags & PPE_FLAG_Y_REFINE) != 0;
   p->lds_t = std::max((size_t)p->txs * 2 * P * sizeof(RedRow<double>), (size_t)p->txs * P * 8);
   if (p->lds_x > 65536 || p->lds_z > lds_limit || p->lds_t > 65536) return false;
   // target-divergence pass
@@ -440,20 +447,29 @@ ppe_status_t launch_chain(ppe_plan_s* p, const Work<TS>& W, int nb, int check) {
   dim3 tgrid((g.hx + p->txs - 1) / p->txs, g.nz, nb);
   dim3 tblock(p->txs * p->pch);
   const bool full = g.ny == p->pch * p->mc;
+  // with refinement (ny > 256 or PPE_FLAG_Y_REFINE) the plain launch takes
+  // the well-conditioned blocks, the refining launch the blocks with a system
+  // of s < kTriTau or the zero mode
+  constexpr double kTriTau = 1e-2;
+#define PPE_TRI(MCV, FULLV, REFV, TAU) \
+  k_tri<TS, MCV, FULLV, REFV><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check, TAU)
+#define PPE_TRI_R(MCV, FULLV)                  \
+  if (p->tri_refine) {                         \
+    PPE_TRI(MCV, FULLV, false, kTriTau);       \
+    PPE_TRI(MCV, FULLV, true, kTriTau);        \
+  } else {                                     \
+    PPE_TRI(MCV, FULLV, false, 0.0);           \
+  }
   PPE_TIMED(p, "k_tri", {
-    if (p->mc == 4 && full)
-      k_tri<TS, 4, true><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
-    else if (p->mc == 4)
-      k_tri<TS, 4, false><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
-    else if (p->mc == 8 && full)
-      k_tri<TS, 8, true><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
-    else if (p->mc == 8)
-      k_tri<TS, 8, false><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
-    else if (full)
-      k_tri<TS, 16, true><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
-    else
-      k_tri<TS, 16, false><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check);
+    if (p->mc == 4 && full) { PPE_TRI_R(4, true); }
+    else if (p->mc == 4) { PPE_TRI_R(4, false); }
+    else if (p->mc == 8 && full) { PPE_TRI_R(8, true); }
+    else if (p->mc == 8) { PPE_TRI_R(8, false); }
+    else if (full) { PPE_TRI_R(16, true); }
+    else { PPE_TRI_R(16, false); }
   });
+#undef PPE_TRI_R
+#undef PPE_TRI
   return launch_fft_z<TS>(p, W, nb, +1, check);
 }
 
