@@ -146,7 +146,10 @@ size_t ppe_plan_workspace_bytes(const ppe_desc_t* desc);
 
 /* Build a plan for `desc` bound to `stream` (a hipStream_t; NULL = the null
  * stream) on the current device.  Allocates the workspace and FP64 twiddle /
- * eigenvalue tables.  On success *out holds the plan; on failure *out is NULL. */
+ * eigenvalue tables; a plan that refines its y solves (ny > 256 or
+ * PPE_FLAG_Y_REFINE) also holds the list of tridiagonal blocks to refine.
+ * All work runs on `stream`.  On success *out holds the plan; on failure *out
+ * is NULL. */
 ppe_status_t ppe_plan(const ppe_desc_t* desc, void* stream, ppe_plan_t* out);
 
 /* Release a plan and its device memory (waits for its stream first). */

@@ -81,6 +81,11 @@ struct ppe_plan_s {
   // every few sweeps, so the host stops enqueuing once all instances converged
   double* conv_host = nullptr;      // [2][kMaxLaunch * kNScal], hipHostMalloc
   hipEvent_t conv_ev[2] = {nullptr, nullptr};
+  // refinement of the y solve: k_tri blocks the plain launch skips (byte per
+  // block, [kz][bx]) and the refining launch's block list (kz << 16 | bx)
+  unsigned char* tri_skip = nullptr;
+  int* tri_rblk = nullptr;
+  int n_rblk = 0;
   long long pstride = 0;
   // device memory
   void* spec = nullptr;
@@ -259,6 +264,49 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
 // FP64 residual buffer: refinement sweeps and the split fixed-point iteration
 bool needs_r64(const ppe_desc_t& d) { return d.precision == PPE_PREC_MIXED || (d.flags & PPE_FLAG_VARCOEF) != 0; }
 
+// Modified wavenumbers of the periodic directions (closed form of the 3-point
+// second difference on its Fourier modes): lam_x over the half spectrum,
+// lam_z over every kz.
+void eig_tables(const ppe_plan_s* p, std::vector<double>& lx, std::vector<double>& lz) {
+  const ppe_desc_t& d = p->d;
+  const double dx = d.lx / d.nx, dz = d.lz / d.nz;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  lx.assign(p->g.hx, 0.0);
+  lz.assign(d.nz, 0.0);
+  for (int a = 0; a < p->g.hx; ++a) {
+    const long double s = sinl(pi * a / d.nx);
+    lx[a] = (double)(-4.0L / ((long double)dx * dx) * s * s);
+  }
+  for (int c = 0; c < d.nz; ++c) {
+    const long double s = sinl(pi * c / d.nz);
+    lz[c] = (double)(-4.0L / ((long double)dz * dz) * s * s);
+  }
+}
+
+// Below this s = -(lam_x + lam_z) dy^2 a y system takes the refining launch:
+// the elimination alone loses ~4 eps / s there (4e-14 at the threshold).
+constexpr double kTriTau = 1e-2;
+
+// The k_tri blocks (TXS consecutive kx at one kz) holding a system with
+// s < kTriTau, or the zero mode: skip mask [kz][bx] for the plain launch and
+// the refining launch's list, one decision per block for both.
+void tri_refine_blocks(const ppe_plan_s* p, const std::vector<double>& lx, const std::vector<double>& lz,
+                       std::vector<unsigned char>& mask, std::vector<int>& list) {
+  const int nbx = (p->g.hx + p->txs - 1) / p->txs;
+  mask.assign((size_t)nbx * p->d.nz, 0);
+  list.clear();
+  for (int kz = 0; kz < p->d.nz; ++kz)
+    for (int bx = 0; bx < nbx; ++bx) {
+      bool small = bx == 0 && kz == 0;
+      for (int kx = bx * p->txs; kx < std::min(p->g.hx, (bx + 1) * p->txs) && !small; ++kx)
+        small = -(lx[kx] + lz[kz]) * p->g.dy2 < kTriTau;
+      if (small) {
+        mask[(size_t)kz * nbx + bx] = 1;
+        list.push_back(kz << 16 | bx);
+      }
+    }
+}
+
 size_t workspace_bytes(const ppe_plan_s* p) {
   const ppe_desc_t& d = p->d;
   const size_t B = (size_t)d.batch;
@@ -272,6 +320,14 @@ size_t workspace_bytes(const ppe_plan_s* p) {
   s += B * (size_t)p->pstride * 8;    // partials
   s += (size_t)(d.nx / 2 + 1) * 8 + (size_t)d.nz * 8;  // eigenvalue tables
   s += (size_t)2 * d.nx * 8 + (size_t)2 * d.nz * 8;    // twiddles
+  if (p->tri_refine) {  // refining blocks of the y solve
+    std::vector<double> lx, lz;
+    std::vector<unsigned char> mask;
+    std::vector<int> list;
+    eig_tables(p, lx, lz);
+    tri_refine_blocks(p, lx, lz, mask, list);
+    s += std::max<size_t>(mask.size(), 8) + std::max<size_t>(list.size() * 4, 8);
+  }
   return s;
 }
 
@@ -294,7 +350,7 @@ void free_plan(ppe_plan_s* p) {
     if (e) (void)hipEventDestroy(e);
   if (p->conv_host) (void)hipHostFree(p->conv_host);
   void* ptrs[] = {p->spec, p->b64, p->r64, p->rowsum, p->colsum, p->scal, p->partial,
-                  p->lamx, p->lamz, p->fx.tw, p->fz.tw};
+                  p->lamx, p->lamz, p->fx.tw, p->fz.tw, p->tri_skip, p->tri_rblk};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -447,28 +503,27 @@ ppe_status_t launch_chain(ppe_plan_s* p, const Work<TS>& W, int nb, int check) {
   dim3 tgrid((g.hx + p->txs - 1) / p->txs, g.nz, nb);
   dim3 tblock(p->txs * p->pch);
   const bool full = g.ny == p->pch * p->mc;
-  // with refinement (ny > 256 or PPE_FLAG_Y_REFINE) the plain launch takes
-  // the well-conditioned blocks, the refining launch the blocks with a system
-  // of s < kTriTau or the zero mode
-  constexpr double kTriTau = 1e-2;
-#define PPE_TRI(MCV, FULLV, REFV, TAU) \
-  k_tri<TS, MCV, FULLV, REFV><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check, TAU)
-#define PPE_TRI_R(MCV, FULLV)                  \
-  if (p->tri_refine) {                         \
-    PPE_TRI(MCV, FULLV, false, kTriTau);       \
-    PPE_TRI(MCV, FULLV, true, kTriTau);        \
-  } else {                                     \
-    PPE_TRI(MCV, FULLV, false, 0.0);           \
-  }
+  // with refinement (ny > 256 or PPE_FLAG_Y_REFINE) the plain launch skips
+  // the blocks holding a system of s < kTriTau or the zero mode, and the
+  // refining launch runs just those, one block per list entry
+  const unsigned char* skip = p->tri_refine ? p->tri_skip : nullptr;
+  const dim3 rgrid(std::max(p->n_rblk, 1), 1, nb);
+#define PPE_TRI(MCV, FULLV)                                                                              \
+  do {                                                                                                   \
+    k_tri<TS, MCV, FULLV, false><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check,    \
+                                                                         skip, nullptr);                 \
+    if (p->tri_refine && p->n_rblk > 0)                                                                  \
+      k_tri<TS, MCV, FULLV, true><<<rgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check,   \
+                                                                          nullptr, p->tri_rblk);         \
+  } while (0)
   PPE_TIMED(p, "k_tri", {
-    if (p->mc == 4 && full) { PPE_TRI_R(4, true); }
-    else if (p->mc == 4) { PPE_TRI_R(4, false); }
-    else if (p->mc == 8 && full) { PPE_TRI_R(8, true); }
-    else if (p->mc == 8) { PPE_TRI_R(8, false); }
-    else if (full) { PPE_TRI_R(16, true); }
-    else { PPE_TRI_R(16, false); }
+    if (p->mc == 4 && full) PPE_TRI(4, true);
+    else if (p->mc == 4) PPE_TRI(4, false);
+    else if (p->mc == 8 && full) PPE_TRI(8, true);
+    else if (p->mc == 8) PPE_TRI(8, false);
+    else if (full) PPE_TRI(16, true);
+    else PPE_TRI(16, false);
   });
-#undef PPE_TRI_R
 #undef PPE_TRI
   return launch_fft_z<TS>(p, W, nb, +1, check);
 }
@@ -703,18 +758,20 @@ ppe_status_t ppe_plan(const ppe_desc_t* desc, void* stream, ppe_plan_t* out) {
     free_plan(p);
     return PPE_ERR_NOMEM;
   }
-  // modified wavenumbers of the periodic directions (closed form of the
-  // 3-point second difference on its Fourier modes)
-  const double dx = d.lx / d.nx, dz = d.lz / d.nz;
-  const long double pi = 3.141592653589793238462643383279502884L;
-  std::vector<double> lx(p->g.hx), lz(d.nz);
-  for (int a = 0; a < p->g.hx; ++a) {
-    const long double s = sinl(pi * a / d.nx);
-    lx[a] = (double)(-4.0L / ((long double)dx * dx) * s * s);
-  }
-  for (int c = 0; c < d.nz; ++c) {
-    const long double s = sinl(pi * c / d.nz);
-    lz[c] = (double)(-4.0L / ((long double)dz * dz) * s * s);
+  std::vector<double> lx, lz;
+  eig_tables(p, lx, lz);
+  if (p->tri_refine) {
+    std::vector<unsigned char> mask;
+    std::vector<int> list;
+    tri_refine_blocks(p, lx, lz, mask, list);
+    p->n_rblk = (int)list.size();
+    ok &= dalloc(p, &p->tri_skip, mask.size()) == hipSuccess;
+    ok &= dalloc(p, &p->tri_rblk, list.size() * 4) == hipSuccess;
+    if (ok) {
+      ok &= hipMemcpy(p->tri_skip, mask.data(), mask.size(), hipMemcpyHostToDevice) == hipSuccess;
+      if (!list.empty())
+        ok &= hipMemcpy(p->tri_rblk, list.data(), list.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    }
   }
   std::vector<double> twx = twiddles(d.nx), twz = twiddles(d.nz);
   ok &= hipMemcpy(p->lamx, lx.data(), lx.size() * 8, hipMemcpyHostToDevice) == hipSuccess;

@@ -91,3 +91,13 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(binding.PPEError, match="not built"):
         binding.load(str(tmp_path / "libppe.so"))
+
+
+def test_y_refine_flag_adds_the_block_tables(lib):
+    """PPE_FLAG_Y_REFINE: the plan also holds a byte per y-solve block and the
+    list of blocks to refine; above 256 rows refinement is on regardless."""
+    plain = ws(nx=64, ny=32, nz=64)
+    flagged = ws(nx=64, ny=32, nz=64, flags=binding.PPE_FLAG_Y_REFINE)
+    assert flagged > plain
+    assert ws(nx=64, ny=512, nz=64, flags=binding.PPE_FLAG_Y_REFINE) == ws(nx=64, ny=512, nz=64)
+    assert ws(flags=4) == 0 and ws(flags=binding.PPE_FLAG_VARCOEF | binding.PPE_FLAG_Y_REFINE) > 0
