@@ -170,6 +170,21 @@ def test_long_y_systems(shape, ybc):
     check(pr, got, rec, ref, tol_p=max(TOL, 2.0 * sens))
 
 
+@pytest.mark.parametrize("ybc", [0, 1])
+@pytest.mark.parametrize("shape", [(8, 2048, 4), (4, 2047, 4)])
+def test_long_y_systems_mixed(shape, ybc):
+    """The refined y solve on FP32 spectra: FP32 rounding of the spectra is
+    removed by the FP64 refinement sweeps, the elimination's loss on the
+    smooth modes by the y refinement inside each solve.  Bounds as for the
+    FP64 path; the divergence is asked for 1e-13 so that p meets its bound."""
+    pr = synth.random_problem(*shape, seed=3 + sum(shape) + ybc, ybc=ybc)
+    (got,), (rec,) = gpu_step([pr], precision=binding.PPE_PREC_MIXED, tol=1e-13, max_refine=4)
+    ref = oracle_step(pr)
+    sens = one_ulp_sensitivity(pr, ref)
+    print(f"oracle one-ulp sensitivity of p: {sens:.2e}", flush=True)
+    check(pr, got, rec, ref, tol_p=max(TOL, 2.0 * sens))
+
+
 def y_only_problem(shape, ybc):
     """u* = 0, uniform density, no history, S a function of y alone: the
     pressure is carried by the kx = kz = 0 system alone, mostly by its
