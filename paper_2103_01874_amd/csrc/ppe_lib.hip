@@ -226,8 +226,11 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
     p->tx /= 2;
   // columns + twiddle table (the plane-sum reduction reuses the column area)
   p->lds_z = std::max((size_t)d.nz * (p->tx + kColPad) * 16, (size_t)p->tx * tcz * 8) + (size_t)d.nz * 16;
-  // tri: P chunks of 2..16 rows, TXS systems per block
-  const int chunk = tune_env("PPE_TUNE_CHUNK") > 0 ? tune_env("PPE_TUNE_CHUNK") : 8;
+  // tri: P chunks of 2..16 rows, TXS systems per block.  A block's time is
+  // mostly its sequential reduced sweep over 2P rows, so the longest chunks
+  // win despite their registers (16 rows against 8: 512x256x512 FP32 spectra
+  // 134 against 196 us per launch; 64x2048x32 FP64 190 against 388 us)
+  const int chunk = tune_env("PPE_TUNE_CHUNK") > 0 ? tune_env("PPE_TUNE_CHUNK") : 16;
   int P = (int)std::lround(d.ny / (double)chunk);
   P = std::max(P, (d.ny + kMaxChunk - 1) / kMaxChunk);
   P = std::min(P, d.ny / 2);

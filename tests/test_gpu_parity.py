@@ -153,8 +153,8 @@ def one_ulp_sensitivity(pr, ref):
 @pytest.mark.parametrize("ybc", [0, 1])
 @pytest.mark.parametrize("shape", LONG_Y)
 def test_long_y_systems(shape, ybc):
-    """ny up to 2048: 256 chunks of 8 rows and a 512-row reduced system per
-    (kx, kz) (one system per block); 1000 = 125 full chunks; 2047 uneven.
+    """ny up to 2048: 128 chunks of 16 rows and a 256-row reduced system per
+    (kx, kz) (two systems per block); 1000 = 62 uneven chunks; 2047 uneven.
 
     The smoothest y mode has eigenvalue 4 sin^2(pi / 2 ny) ~ (pi / ny)^2, so
     random inputs whose rounding reaches that mode determine p only to about
