@@ -139,23 +139,42 @@ def copy_gbs(dev, nbytes: int = 1 << 30, reps: int = 5) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(pr, budget_s: float = 12.0):
-    """The FP64 oracle on the same workload, timed on the host."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pr, budget_s: float = 12.0, single_budget_s: float = 6.0):
+    """The FP64 oracle on the same workload, timed on the host: with up to 16
+    FFT workers, and again with one."""
     import oracle as O
 
-    workers = max(1, min(16, os.cpu_count() or 1))
     g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=pr.ybc)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        O.ppe_step(g, pr.rho0, pr.dt, *pr.fields(), workers=workers)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 20:
-            break
+
+    def timed(workers, budget):
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            O.ppe_step(g, pr.rho0, pr.dt, *pr.fields(), workers=workers)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget or steps >= 20:
+                return steps, el
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    steps, el = timed(workers, budget_s)
+    s1, e1 = timed(1, single_budget_s)
     return {"value": pr.npts * steps / el, "unit": "points/s", "cores": workers, "kind": "oracle",
             "sample": f"{steps} full step(s) of the same workload ({pr.nx}x{pr.ny}x{pr.nz}) in {el:.1f} s; "
-                      f"scipy.fft with {workers} workers, numpy elementwise work on one thread"}
+                      f"scipy.fft with {workers} workers, numpy elementwise work on one thread",
+            "single_worker": {"value": pr.npts * s1 / e1, "unit": "points/s", "cores": 1,
+                              "sample": f"{s1} full step(s) in {e1:.1f} s, scipy.fft with 1 worker"},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def counter_traffic(workload: str, kernel: str):
