@@ -282,6 +282,7 @@ def run_serve(args, precision, max_refine, desc, n_requests=500):
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    max_points = args.max_points if args.max_points > 0 else None
     pool = {}
     for si, shape in enumerate(synth.SERVE_SHAPES):
         pool[shape] = []
@@ -302,17 +303,17 @@ def run_serve(args, precision, max_refine, desc, n_requests=500):
     be = GpuBackend(n_slots=4, precision=precision, tol=1e-12, max_refine=max_refine)
     budget = 64 << 30
     # warm the plan cache and the kernels once
-    warm = Server(be, budget, n_slots=4, max_group=8)
+    warm = Server(be, budget, n_slots=4, max_group=8, max_points=max_points)
     warm.run(requests([0.0] * n_requests))
     results = {}
-    srv = Server(be, budget, n_slots=4, max_group=8)
+    srv = Server(be, budget, n_slots=4, max_group=8, max_points=max_points)
     srv.plans, srv.used = warm.plans, sum(v[1] for v in warm.plans.values())
     m = srv.run(requests([0.0] * n_requests))
     results["saturated"] = m
     rate_sat = m["requests_per_s"]
     for frac in (0.5, 0.8):
         reqs = requests(poisson_arrivals(n_requests, frac * rate_sat, 77))
-        srv2 = Server(be, budget, n_slots=4, max_group=8)
+        srv2 = Server(be, budget, n_slots=4, max_group=8, max_points=max_points)
         srv2.plans, srv2.used = srv.plans, sum(v[1] for v in srv.plans.values())
         results[f"poisson_{frac}"] = dict(srv2.run(reqs), rate_per_s=frac * rate_sat)
         bad = [r for r in reqs if r.status != 0]
@@ -331,6 +332,9 @@ def main():
     ap.add_argument("--workload", default="sheet_256x128x256_fp64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed roofline pass")
+    ap.add_argument("--max-points", type=int, default=256 * 128 * 256,
+                    help="serving: cap on the grid points of one batched group (0: none); the default, one "
+                         "256x128x256 instance, cut p99 by a fifth to a third against no cap")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run a plain device copy of this many bytes 3 times (counter calibration)")
     args = ap.parse_args()

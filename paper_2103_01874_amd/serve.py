@@ -104,11 +104,16 @@ class Backend:
 
 class Server:
     def __init__(self, backend: Backend, budget_bytes: int, n_slots: int = 4, max_group: int = 8,
-                 clock: Callable[[], float] = time.perf_counter, idle: Optional[Callable[[], None]] = None):
+                 clock: Callable[[], float] = time.perf_counter, idle: Optional[Callable[[], None]] = None,
+                 max_points: Optional[int] = None):
         self.b = backend
         self.budget = int(budget_bytes)
         self.n_slots = int(n_slots)
         self.max_group = int(max_group)
+        # cap on the grid points of one group (at least one request): a large
+        # instance already fills the GPU, and a group of them only makes the
+        # requests queued behind it wait longer
+        self.max_points = None if max_points is None else int(max_points)
         self.clock = clock
         self.idle = idle
         self.used = 0                                 # bytes held by admitted requests and cached plans
@@ -173,7 +178,10 @@ class Server:
             if slot in self.inflight:
                 continue
             head = self.ready[0]
-            same = [r for r in self.ready if r.plan_key == head.plan_key][: self.max_group]
+            cap = self.max_group
+            if self.max_points is not None:
+                cap = max(1, min(cap, self.max_points // math.prod(head.shape)))
+            same = [r for r in self.ready if r.plan_key == head.plan_key][:cap]
             # batch sizes are powers of two so that few plans serve every group
             g = 1 << (len(same).bit_length() - 1)
             group = same[:g]

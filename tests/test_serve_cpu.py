@@ -70,10 +70,10 @@ def mk(rid, shape, t):
     return Request(rid=rid, shape=shape, inputs=None, rho0=1.0, dt=1e-3, arrival=t)
 
 
-def run(reqs, budget=10**12, slots=2, max_group=8, **kw):
+def run(reqs, budget=10**12, slots=2, max_group=8, max_points=None, **kw):
     clk = FakeClock()
     be = FakeBackend(clk, **kw)
-    srv = Server(be, budget, n_slots=slots, max_group=max_group, clock=clk, idle=clk.tick)
+    srv = Server(be, budget, n_slots=slots, max_group=max_group, clock=clk, idle=clk.tick, max_points=max_points)
     m = srv.run(reqs)
     return srv, be, m
 
@@ -171,3 +171,23 @@ def test_boundaries_and_lengths_split_groups():
         assert len({reqs[r].plan_key for r in rids}) == 1
     groups = group_by_shape(reqs, 8)
     assert sorted(len(g) for g in groups) == [1, 2, 3]
+
+
+def test_points_cap_limits_large_groups_only():
+    """max_points bounds a group's grid points (at least one request): large
+    shapes go out in small groups, small shapes still fill max_group."""
+    reqs = [mk(i, (32, 32, 32), 0.0) for i in range(8)] + [mk(8 + i, (128, 64, 128), 0.0) for i in range(4)]
+    srv, be, m = run(reqs, slots=1, max_points=2 * 128 * 64 * 128)
+    assert m["served"] == 12
+    groups = [sorted(reqs[i].shape for i in ids) for _, ids in be.launches]
+    assert sorted(len(g) for g in groups if g[0] == (32, 32, 32)) == [8]
+    assert sorted(len(g) for g in groups if g[0] == (128, 64, 128)) == [2, 2]
+    # a cap below one request still launches it alone
+    srv, be, m = run([mk(0, (128, 64, 128), 0.0)], slots=1, max_points=10)
+    assert m["served"] == 1 and [len(ids) for _, ids in be.launches] == [1]
+    # the first large requests finish before the rest of their shape: lower mean latency
+    reqs2 = [mk(i, (128, 64, 128), 0.0) for i in range(4)] + [mk(4, (32, 32, 32), 0.0)]
+    _, _, capped = run(reqs2, slots=1, max_points=2 * 128 * 64 * 128)
+    reqs3 = [mk(i, (128, 64, 128), 0.0) for i in range(4)] + [mk(4, (32, 32, 32), 0.0)]
+    _, _, whole = run(reqs3, slots=1)
+    assert capped["mean_ms"] < whole["mean_ms"]
