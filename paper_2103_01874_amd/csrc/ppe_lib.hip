@@ -1172,7 +1172,13 @@ ppe_status_t ppe_predict(ppe_plan_t p, const ppe_predict_t* in, double* const* u
       t.dt = q.dt;
     }
     PPE_TIMED(p, "k_predict_u", (k_predict<0><<<dim3(blocks, 1, nb), 256, 0, p->stream>>>(tab, g)));
-    PPE_TIMED(p, "k_predict_v", (k_predict<1><<<dim3(blocks, 1, nb), 256, 0, p->stream>>>(tab, g)));
+    PPE_TIMED(p, "k_predict_v", {
+      k_predict<1><<<dim3(blocks, 1, nb), 256, 0, p->stream>>>(tab, g);
+      if (g.ybc == 1) {  // the outflow top face
+        const unsigned tblocks = (unsigned)(((long long)g.nx * g.nz + 255) / 256);
+        k_predict_vtop<<<dim3(tblocks, 1, nb), 256, 0, p->stream>>>(tab, g);
+      }
+    });
     PPE_TIMED(p, "k_predict_w", (k_predict<2><<<dim3(blocks, 1, nb), 256, 0, p->stream>>>(tab, g)));
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
