@@ -89,7 +89,9 @@ def algorithmic_bytes(kernel: str, nx: int, ny: int, nz: int, precision: int, mo
     assembles only c), p_aliased (k_correct given one array for p, p^n and
     p^{n-1}), first_frac (the share of k_resid_var launches that form p_0 from
     p^n, p^{n-1}), viscous_separate (predictor given its own viscous-term
-    velocities)."""
+    velocities).  mode_update: for k_c2r the refinement launch (p read and
+    written), for k_r2c the refinement launch (the residual as its source, in
+    the spectrum's precision)."""
     ctx = ctx or {}
     N = nx * ny * nz
     Nv = nx * (ny + 1) * nz
@@ -101,12 +103,13 @@ def algorithmic_bytes(kernel: str, nx: int, ny: int, nz: int, precision: int, mo
     table = {
         # u*, v*, w*, rho, p^n, p^{n-1}, S -> b; without the split term u*, v*, w*, S -> c
         "k_rhs": (8 * (6 * N + Nv) if split else 8 * (3 * N + Nv)) + 8 * N,
-        "k_r2c": 8 * N + cs * Ns,                      # b (or r) -> half spectrum
+        # b, or the refinement residual (spectrum precision) -> half spectrum
+        "k_r2c": (cs // 2 if mode_update else 8) * N + cs * Ns,
         "k_fft_z_fwd": 2 * cs * Ns,
         "k_fft_z_inv": 2 * cs * Ns,
         "k_tri": 2 * cs * Ns,
         "k_c2r": cs * Ns + 8 * N + (8 * N if mode_update else 0),
-        "k_resid": 3 * 8 * N,                          # b, p -> r
+        "k_resid": 16 * N + (cs // 2) * N,             # b, p -> r (spectrum precision)
         # c, rho, p -> r; the first sweep reads p^n, p^{n-1} instead of p and also writes p
         "k_resid_var": (1 - first) * 32 * N + first * 48 * N,
         # u*,v*,w*,rho,p^n,p^{n-1},p,S -> u,v,w (one pressure array when aliased)
@@ -248,7 +251,7 @@ def run_batch(args, precision, max_refine, desc):
             nx, ny, nz = g[0].shape
             for k, v in pl.profile_read().items():
                 b = algorithmic_bytes(k, nx, ny, nz, precision) * len(g)
-                if k == "k_c2r" and max_refine > 0:
+                if k in ("k_c2r", "k_r2c") and max_refine > 0:
                     b = 0.5 * len(g) * (algorithmic_bytes(k, nx, ny, nz, precision, False)
                                         + algorithmic_bytes(k, nx, ny, nz, precision, True))
                 t = tot.setdefault(k, [0.0, 0.0])
@@ -473,8 +476,8 @@ def main():
         def launch_bytes(k):
             if k == "k_c2r" and varcoef:  # every sweep updates p
                 return algorithmic_bytes(k, pr.nx, pr.ny, pr.nz, precision, True, ctx=ctx)
-            if k == "k_c2r" and max_refine > 0:
-                # one launch writes p, the refinement launches update it: average
+            if k in ("k_c2r", "k_r2c") and max_refine > 0:
+                # the first launch solves for p, the refinement launches correct it: average
                 nu = min(max_refine, rec["iters"])
                 return (algorithmic_bytes(k, pr.nx, pr.ny, pr.nz, precision, False, ctx=ctx)
                         + nu * algorithmic_bytes(k, pr.nx, pr.ny, pr.nz, precision, True, ctx=ctx)) / (1 + nu)

@@ -570,15 +570,18 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   PPE_TIMED(p, "k_c2r",
             PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 0, 0))));
   if (mixed) {
+    // the refinement residual in the spectrum's precision (the first half of
+    // the FP64 residual buffer)
+    TS* rs = reinterpret_cast<TS*>(p->r64);
     for (int it = 0; it < p->d.max_refine; ++it) {
       PPE_TIMED(p, "k_resid",
                 PPE_PPT_SWITCH(p->mres.ppt, (k_resid<TS, PPT><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
                                                                 march_lds(p->mres, 1), p->stream>>>(tab, g, p->mres.m, W,
-                                                                                                    p->r64))));
+                                                                                                    rs))));
       finish(p, tab, inst0, nb, p->mres.grid, FIN_RESID, 1);
       PPE_TIMED(p, "k_r2c",
                 PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
-                                       tab, g, fx, W, p->r64, p->rp, 1, FinishArgs{0, 0.0}))));
+                                       tab, g, fx, W, static_cast<const TS*>(rs), p->rp, 1, FinishArgs{0, 0.0}))));
       st = launch_chain<TS>(p, W, nb, 1);
       if (st != PPE_OK) return st;
       PPE_TIMED(p, "k_c2r",

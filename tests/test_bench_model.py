@@ -27,6 +27,14 @@ def test_spectral_passes_per_precision():
         assert ab("k_tri", prec) == ab("k_fft_z_fwd", prec) == ab("k_fft_z_inv", prec) == 2 * cs * NS
         assert ab("k_c2r", prec) == cs * NS + 8 * N
         assert ab("k_c2r", prec, mode_update=True) == cs * NS + 16 * N  # p read back
+        # the refinement's row transform reads the residual in the spectrum's precision
+        assert ab("k_r2c", prec, mode_update=True) == (cs // 2) * N + cs * NS
+
+
+def test_refinement_residual_is_stored_in_the_spectrum_precision():
+    # b, p read in FP64; r written in FP32 for FP32 spectra
+    assert ab("k_resid", 1) == 16 * N + 4 * N
+    assert ab("k_resid", 0) == 24 * N
 
 
 def test_fixed_point_residual_first_and_later_sweeps():
