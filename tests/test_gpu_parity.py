@@ -328,6 +328,21 @@ def test_batched_equals_single_bitwise():
         assert br == sr
 
 
+@pytest.mark.parametrize("precision", [binding.PPE_PREC_FP64, binding.PPE_PREC_MIXED])
+@pytest.mark.parametrize("ybc", [0, 1])
+def test_batched_refined_y_solve_equals_single_bitwise(ybc, precision):
+    """ny > 256: the refining tridiagonal launch runs one block per listed
+    (kx, kz) block and instance; a batch of three equals three single calls."""
+    probs = [synth.random_problem(8, 300, 6, seed=60 + i, ybc=ybc) for i in range(3)]
+    batched, brecs = gpu_step(probs, precision=precision, tol=1e-13, max_refine=3)
+    for pr, b, br in zip(probs, batched, brecs):
+        (single,), (sr,) = gpu_step([pr], precision=precision, tol=1e-13, max_refine=3)
+        for k in ("p", "u", "v", "w"):
+            assert np.array_equal(b[k], single[k]), k
+        assert br == sr
+    check(probs[1], batched[1], brecs[1], oracle_step(probs[1]))
+
+
 def test_residual_entry_point():
     torch = _torch()
     pr = synth.sheet_problem(24, 12, 18, seed=9)
