@@ -78,6 +78,38 @@ def test_ring_equals_explicit_history_and_oracle_loop(ybc):
     plan.close()
 
 
+@pytest.mark.parametrize("ybc", [0, 1])
+def test_ring_256x128x256_against_oracle_loop(ybc):
+    """The time-loop benchmark's grid: two ring steps against the oracle's
+    time loop, every point."""
+    torch = _torch()
+    shape = (256, 128, 256)
+    steps = step_inputs(shape, ybc, 2)
+    pr0 = steps[0]
+    plan = binding.Plan(pr0.nx, pr0.ny, pr0.nz, pr0.lx, pr0.ly, pr0.lz, ybc=ybc)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    ring = binding.Ring(plan, [dev(pr0.pn)], [dev(pr0.pnm1)])
+    g = O.Grid(pr0.nx, pr0.ny, pr0.nz, pr0.lx, pr0.ly, pr0.lz, ybc=ybc)
+    on, om = pr0.pn.copy(), pr0.pnm1.copy()
+    for t, pr in enumerate(steps):
+        f = binding.to_device(pr)
+        u, v, w = torch.empty_like(f["us"]), torch.empty_like(f["vs"]), torch.empty_like(f["ws"])
+        info, _ = ring.step([pr.rho0], [pr.dt], [f["us"]], [f["vs"]], [f["ws"]], [f["rho"]], [f["S"]], [u], [v], [w])
+        p = torch.empty_like(f["rho"])
+        ring.read(0, [p])
+        torch.cuda.synchronize()
+        ref = O.ppe_step(g, pr.rho0, pr.dt, pr.us, pr.vs, pr.ws, pr.rho, on, om, pr.S)
+        om, on = on, ref["p"]
+        ep = rel(p.cpu().numpy(), ref["p"])
+        eu = rel(u.cpu().numpy() - pr.us, ref["u"] - pr.us)
+        rec = binding.decode_info(info)[0]
+        print(f"ybc={ybc} step {t}: eps_p={ep:.2e} eps_u={eu:.2e} eps_div={rec['res_rel']:.2e}", flush=True)
+        assert ep <= 1e-12 and eu <= 1e-12 and rec["status"] == 0 and rec["res_rel"] <= 1e-12
+        del f, u, v, w, p
+    ring.close()
+    plan.close()
+
+
 def test_ring_without_previous_pressure_uses_p_n():
     torch = _torch()
     pr = synth.sheet_problem(16, 8, 12, seed=31)

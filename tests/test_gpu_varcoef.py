@@ -125,6 +125,19 @@ def test_sheet_contracts_within_the_bound_and_batches_bitwise():
         assert np.array_equal(alone, ps[i]) and np.array_equal(Ha[0], H[i])
 
 
+def test_fixed_sweeps_sheet_256x128x256():
+    """The 256x128x256 sheet of the fixed-point benchmark, in its launch
+    configuration: four sweeps against the oracle's iterates, every point."""
+    pr = synth.sheet_256()
+    K = 4
+    (p,), (rec,), H, _ = gpu_varcoef([pr], K, 0.0)
+    _, ref = oracle_fp(pr, K)
+    print(f"eps_p={rel(p, ref['p']):.2e} res={H[0, :K + 1]}", flush=True)
+    assert rel(p, ref["p"]) <= 1e-12
+    r = np.array(ref["res"])
+    assert np.all(np.abs(H[0][: K + 1] - r[: K + 1]) <= 1e-8 * r[: K + 1])
+
+
 def test_not_converged_status():
     pr = synth.random_problem(8, 4, 8, seed=9)
     (p,), (rec,), H, _ = gpu_varcoef([pr], 3, 1e-14)
