@@ -160,8 +160,8 @@ bool march_shape(const ppe_desc_t& d, int points, int max_txt, const char* env, 
   M.ntj = (d.ny + M.tj - 1) / M.tj;
   const int target = tune_env("PPE_TUNE_MARCH_BLOCKS") > 0 ? tune_env("PPE_TUNE_MARCH_BLOCKS") : 2048;
   int nkc = std::max(1, (target + M.ntx * M.ntj - 1) / (M.ntx * M.ntj));
-  // and at most 16 planes per block: with fewer, longer marches the last
-  // round of resident blocks leaves the GPU idle for longer (512x256x512:
+  // and at most 16 planes per block: with fewer, longer marches the final
+  // set of resident blocks leaves the GPU idle for longer (512x256x512:
   // 128 planes per block, k_correct 1387 us; 16 planes, 1306 us)
   nkc = std::max(nkc, (d.nz + 15) / 16);
   nkc = std::min(nkc, std::max(1, d.nz / 2));
