@@ -198,6 +198,10 @@ class Plan:
             _check(self.lib.ppe_plan(ctypes.byref(self.desc), ctypes.c_void_p(self.stream.cuda_stream),
                                      ctypes.byref(self._h)), "ppe_plan")
         self.nx, self.ny, self.nz, self.batch = int(nx), int(ny), int(nz), int(batch)
+        # what every field tensor must match (checked on each call, cheaply)
+        self._shape_c = torch.Size((self.nz, self.ny, self.nx))
+        self._shape_v = torch.Size((self.nz, self.ny + 1, self.nx))
+        self._dev_index = self.device.index
 
     @property
     def workspace_bytes(self) -> int:
@@ -236,26 +240,24 @@ class Plan:
             pass
 
     # -- validation ---------------------------------------------------------
-    def _cell(self, t, name):
+    def _field(self, t, shape, name, i):
         torch = self._torch
-        shp = (self.nz, self.ny, self.nx)
-        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device \
-                or tuple(t.shape) != shp or not t.is_contiguous():
-            raise PPEError(f"{name}: expected contiguous float64 {shp} on {self.device}")
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.shape != shape \
+                or not t.is_cuda or t.get_device() != self._dev_index or not t.is_contiguous():
+            raise PPEError(f"{name}[{i}]: expected contiguous float64 {tuple(shape)} on {self.device}")
         return t
 
+    def _cell(self, t, name):
+        return self._field(t, self._shape_c, name, 0)
+
     def _vface(self, t, name):
-        torch = self._torch
-        shp = (self.nz, self.ny + 1, self.nx)
-        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device \
-                or tuple(t.shape) != shp or not t.is_contiguous():
-            raise PPEError(f"{name}: expected contiguous float64 {shp} on {self.device}")
-        return t
+        return self._field(t, self._shape_v, name, 0)
 
     def _batch(self, seq, name, v=False):
         if len(seq) != self.batch:
             raise PPEError(f"{name}: expected {self.batch} tensors, got {len(seq)}")
-        return [(self._vface if v else self._cell)(t, f"{name}[{i}]") for i, t in enumerate(seq)]
+        shape = self._shape_v if v else self._shape_c
+        return [self._field(t, shape, name, i) for i, t in enumerate(seq)]
 
     def new_info(self):
         return self._torch.zeros(self.batch * 8, dtype=self._torch.float64, device=self.device)
@@ -319,7 +321,7 @@ class Plan:
             for k in SOURCE_FIELDS:
                 if d.get(k) is None:
                     raise PPEError(f"sources[{i}]: missing {k}")
-                setattr(recs[i], k, self._cell(d[k], f"{k}[{i}]").data_ptr())
+                setattr(recs[i], k, self._field(d[k], self._shape_c, k, i).data_ptr())
             m = d.get("under")
             if m is not None:
                 if not isinstance(m, torch.Tensor) or m.dtype != torch.uint8 or m.device != self.device \
