@@ -61,6 +61,7 @@ WORKLOADS = {
                                           "same-shape instances batched per launch"),
     "batch_48_fp64": ("batch_48", 0, 0, "the same 48 sheets as batch_48_mixed through the FP64 direct solve, "
                                          "same-shape instances batched per launch"),
+    "serve_fp64": ("serve", 0, 0, "the serve_mixed request stream through the FP64 direct solve"),
     "serve_mixed": ("serve", 1, 1, "Poisson-arrival stream of sheets over {32^3 .. 256x128x256}, FP32 spectra + "
                                    "FP64 refinement to 1e-12, 64 GB HBM budget, plans cached, continuous "
                                    "batching on 4 streams"),
