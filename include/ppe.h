@@ -84,8 +84,11 @@ typedef enum {
 
 /* Plan options (ppe_desc_t.flags). */
 #define PPE_FLAG_VARCOEF 1   /* also allocate the FP64 residual buffer that
-                                ppe_solve_varcoef needs (always present for
-                                PPE_PREC_MIXED): 8 bytes per cell and instance */
+                                ppe_solve_varcoef and the ring's split defect
+                                need: 8 bytes per cell and instance, for either
+                                precision (a PPE_PREC_MIXED plan otherwise
+                                holds 4 bytes per cell for the FP32 residual of
+                                its refinement, which those calls cannot use) */
 #define PPE_FLAG_Y_REFINE 2  /* follow every y tridiagonal solve of a system
                                 whose smallest eigenvalue is below about 1e-2
                                 (s + the lowest y mode, Sec. 5.4 scaling) by
@@ -187,7 +190,7 @@ ppe_status_t ppe_solve(ppe_plan_t plan, const double* rho0, const double* dt,
  * Stops when the relative residual
  *   res_k = ||rho0 [(1/dt)(D u* - S_c) - D((1/rho_f) G p_k)]||_2 / ||(rho0/dt)(D u* - S_c)||_2
  * reaches tol, or after max_iters updates (>= 0; 0 only evaluates res_0).
- * The plan needs PPE_FLAG_VARCOEF or PPE_PREC_MIXED (else PPE_ERR_ARG).
+ * The plan needs PPE_FLAG_VARCOEF, for either precision (else PPE_ERR_ARG).
  *   p     : output, must not alias p^n or p^{n-1}
  *   tol   : 0 runs max_iters sweeps without a convergence test
  *   info  : status (PPE_ERR_NOT_CONVERGED if tol > 0 and res > tol after
@@ -288,7 +291,7 @@ ppe_status_t ppe_ring_create(ppe_plan_t plan, const double* const* pn, const dou
  * residual of the variable-coefficient problem, Eq. (25), for p_hat ([b][0])
  * and for the split pressure p^{n+1} ([b][1]) -- how far the split is from
  * the variable-density projection this step (Sec. 5.4).  It needs the plan's
- * residual buffer (PPE_FLAG_VARCOEF or PPE_PREC_MIXED) and takes the
+ * FP64 residual buffer (PPE_FLAG_VARCOEF) and takes the
  * pressure from one sweep of ppe_solve_varcoef (equal to ppe_solve's to
  * rounding). */
 ppe_status_t ppe_ring_step(ppe_ring_t ring, const double* rho0, const double* dt,

@@ -77,6 +77,7 @@ struct ppe_plan_s {
     int tslots = 0;  // LDS slots of a tile plane with its halo ring
   } mrhs, mcor, mres;
   double* r64 = nullptr;   // refinement / fixed-point residual (mixed, or PPE_FLAG_VARCOEF)
+  int r64_elem = 0;        // its bytes per cell: 8 (FP64, PPE_FLAG_VARCOEF) or 4 (mixed refinement only)
   // fixed-point iteration: convergence flags copied to pinned host memory
   // every few sweeps, so the host stops enqueuing once all instances converged
   double* conv_host = nullptr;      // [2][kMaxLaunch * kNScal], hipHostMalloc
@@ -269,7 +270,13 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
 }
 
 // FP64 residual buffer: refinement sweeps and the split fixed-point iteration
-bool needs_r64(const ppe_desc_t& d) { return d.precision == PPE_PREC_MIXED || (d.flags & PPE_FLAG_VARCOEF) != 0; }
+// Bytes per cell of the residual buffer: the fixed-point iteration keeps an
+// FP64 residual; the mixed refinement alone stores it in FP32.
+int r64_elem_bytes(const ppe_desc_t& d) {
+  if ((d.flags & PPE_FLAG_VARCOEF) != 0) return 8;
+  return d.precision == PPE_PREC_MIXED ? 4 : 0;
+}
+bool needs_r64(const ppe_desc_t& d) { return r64_elem_bytes(d) > 0; }
 
 // Modified wavenumbers of the periodic directions (closed form of the 3-point
 // second difference on its Fourier modes): lam_x over the half spectrum,
@@ -320,7 +327,7 @@ size_t workspace_bytes(const ppe_plan_s* p) {
   size_t s = 0;
   s += B * (size_t)p->g.spec_elems * spec_elem_bytes(&d);
   s += B * (size_t)p->g.npts * 8;                                       // b64
-  if (needs_r64(d)) s += B * (size_t)p->g.npts * 8;                     // r64
+  s += B * (size_t)p->g.npts * r64_elem_bytes(d);                       // r64
   s += B * (size_t)d.ny * d.nz * 8;   // rowsum
   s += B * (size_t)d.ny * 8;          // colsum
   s += B * (size_t)kNScal * 8;        // scalars
@@ -751,7 +758,8 @@ ppe_status_t ppe_plan(const ppe_desc_t* desc, void* stream, ppe_plan_t* out) {
   ok &= dalloc(p, (char**)&p->spec, B * (size_t)p->g.spec_elems * spec_elem_bytes(&d)) == hipSuccess;
   ok &= dalloc(p, &p->b64, B * (size_t)p->g.npts * 8) == hipSuccess;
   if (needs_r64(d)) {
-    ok &= dalloc(p, &p->r64, B * (size_t)p->g.npts * 8) == hipSuccess;
+    p->r64_elem = r64_elem_bytes(d);
+    ok &= dalloc(p, &p->r64, B * (size_t)p->g.npts * p->r64_elem) == hipSuccess;
     ok &= hipHostMalloc((void**)&p->conv_host, 2 * kMaxLaunch * kNScal * sizeof(double), hipHostMallocDefault) ==
           hipSuccess;
     for (hipEvent_t& e : p->conv_ev) ok &= hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
@@ -854,7 +862,7 @@ ppe_status_t ppe_solve_varcoef(ppe_plan_t p, const double* rho0, const double* d
                                double* const* pout, ppe_info_t* info, int32_t max_iters, double tol,
                                double* hist) {
   if (!p || !rho0 || !dt || !info) return PPE_ERR_ARG;
-  if (!p->r64) return PPE_ERR_ARG;  // plan built without the residual buffer
+  if (!p->r64 || p->r64_elem != 8) return PPE_ERR_ARG;  // plan built without the FP64 residual buffer
   if (max_iters < 0 || max_iters > 100000 || !(tol >= 0)) return PPE_ERR_ARG;
   const int B = p->d.batch;
   if (!ptrs_ok((const void* const*)us, B) || !ptrs_ok((const void* const*)vs, B) ||

@@ -81,8 +81,8 @@ def test_workspace_accounts_for_precision_and_batch(lib):
     spec64 = 64 * 32 * 40 * 16
     spec32 = 64 * 32 * 48 * 8
     assert b > 3 * a
-    # mixed: FP32 spectrum plus the FP64 refinement residual buffer
-    assert m - a == spec32 - spec64 + 64 * 32 * 64 * 8
+    # mixed: FP32 spectrum plus the refinement residual, stored in FP32
+    assert m - a == spec32 - spec64 + 64 * 32 * 64 * 4
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
@@ -101,3 +101,17 @@ def test_y_refine_flag_adds_the_block_tables(lib):
     assert flagged > plain
     assert ws(nx=64, ny=512, nz=64, flags=binding.PPE_FLAG_Y_REFINE) == ws(nx=64, ny=512, nz=64)
     assert ws(flags=4) == 0 and ws(flags=binding.PPE_FLAG_VARCOEF | binding.PPE_FLAG_Y_REFINE) > 0
+
+
+def test_residual_buffer_sizes(lib):
+    """FP64 residual (8 B per cell) for the fixed-point iteration; a mixed plan
+    without PPE_FLAG_VARCOEF holds only the FP32 residual of its refinement."""
+    n = 32 * 32 * 32
+    fp64 = ws()
+    assert ws(flags=binding.PPE_FLAG_VARCOEF) - fp64 == 8 * n
+    mixed = ws(precision=binding.PPE_PREC_MIXED)
+    assert ws(precision=binding.PPE_PREC_MIXED, flags=binding.PPE_FLAG_VARCOEF) - mixed == 4 * n
+    # FP32 spectra (half of FP64's, in 128-byte tiles) plus the 4-byte residual
+    spec64 = 32 * 32 * 24 * 16   # 17 kx columns in tiles of 8
+    spec32 = 32 * 32 * 32 * 8    # 17 kx columns in tiles of 16
+    assert mixed - fp64 == spec32 - spec64 + 4 * n

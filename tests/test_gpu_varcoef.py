@@ -157,3 +157,10 @@ def test_needs_the_residual_buffer():
     plan.close()
     assert binding.workspace_bytes(binding.make_desc(8, 4, 8, flags=binding.PPE_FLAG_VARCOEF)) - \
         binding.workspace_bytes(binding.make_desc(8, 4, 8)) == 8 * 8 * 4 * 8
+    # a mixed plan holds only the FP32 residual of its refinement: it needs the
+    # flag for the fixed-point iteration too
+    mixed = binding.Plan(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, precision=binding.PPE_PREC_MIXED)
+    with pytest.raises(binding.PPEError):
+        mixed.solve_varcoef([pr.rho0], [pr.dt], [f["us"]], [f["vs"]], [f["ws"]], [f["rho"]], [f["pn"]],
+                            [f["pnm1"]], [f["S"]], [p], 3, 1e-12)
+    mixed.close()
