@@ -104,8 +104,10 @@ typedef enum {
 /* Precision of the spectral passes (FFTs and tridiagonal sweeps). */
 typedef enum {
   PPE_PREC_FP64 = 0,   /* FP64 storage and arithmetic: the direct solve */
-  PPE_PREC_MIXED = 1   /* FP32 spectra in memory, FP64 arithmetic in registers,
-                          FP64 residual, zero mode, gauge and refinement */
+  PPE_PREC_MIXED = 1   /* FP32 spectra in memory, FP64 arithmetic in registers;
+                          the residual is formed and its norm taken in FP64
+                          (stored in FP32 for the correction solve), and the
+                          zero mode, gauge and update of p are FP64 */
 } ppe_precision_t;
 
 typedef struct {
@@ -169,7 +171,7 @@ ppe_status_t ppe_plan_set_stream(ppe_plan_t plan, void* stream);
  *             PPE_YBC_WALLS)
  *   info    : device array of `batch` records (output)
  * For PPE_PREC_MIXED the first solve uses FP32 spectra and is refined with
- * FP64 residuals until `tol` or `max_refine`. */
+ * residuals formed in FP64 until `tol` or `max_refine`. */
 ppe_status_t ppe_solve(ppe_plan_t plan, const double* rho0, const double* dt,
                        const double* const* us, const double* const* vs, const double* const* ws,
                        const double* const* rho, const double* const* pn, const double* const* pnm1,
