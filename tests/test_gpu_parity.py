@@ -6,7 +6,11 @@ projection step is specified to), measured as
   eps_du = ||(u - u*) - (u_o - u*)|| / ||u_o - u*||   (the correction itself)
   eps_div = ||D u - S_c|| / ||D u* - S_c||     (from the library's own check)
 The FP64 path is expected near 1e-14; the mixed path must reach 1e-12 after
-refinement.
+refinement.  Where the problem's own FP64 conditioning puts 1e-12 out of
+reach of any solver (random fields at ny ~ 2048, pressures dominated by a mode
+of tiny eigenvalue), the bound is taken from the oracle on the same input --
+its change under a one-ulp move of the inputs, or its own divergence figure --
+never from the GPU; each such test states which.
 """
 import numpy as np
 import pytest
