@@ -177,6 +177,22 @@ ppe_status_t ppe_solve(ppe_plan_t plan, const double* rho0, const double* dt,
                        const double* const* rho, const double* const* pn, const double* const* pnm1,
                        const double* const* S, double* const* p, ppe_info_t* info);
 
+/* Right-hand side of Eq. (29) alone, with Eq. (27) (Sec. 5.4):
+ *   b = (rho0/dt)(D u* - S) + D((1 - rho0/rho_f) G p_hat),  p_hat = 2 p^n - p^{n-1},
+ * zero flux through the zero-flux y faces (an outflow top face carries the
+ * ghost value -p_hat), before any compatibility projection.  The same pass
+ * ppe_solve starts with, for callers that assemble here and solve elsewhere,
+ * and for checking the assembly on its own.
+ *   rho0, dt, us .. S : as for ppe_solve
+ *   b    : host array of `batch` device pointers (output, [nz][ny][nx])
+ *   info : device array of `batch` records; rho0_used and compat_defect
+ *          (mean(D u* - S) with zero-flux ends, else 0) are written, the rest
+ *          cleared */
+ppe_status_t ppe_rhs(ppe_plan_t plan, const double* rho0, const double* dt,
+                     const double* const* us, const double* const* vs, const double* const* ws,
+                     const double* const* rho, const double* const* pn, const double* const* pnm1,
+                     const double* const* S, double* const* b, ppe_info_t* info);
+
 /* Pressure of the variable-coefficient problem, Eq. (25), by the split
  * fixed-point iteration (Sec. 5.4: the split is exact when grad p_hat equals
  * grad p^{n+1}, so the pressure of Eq. 25 is the fixed point of the split
@@ -205,7 +221,7 @@ ppe_status_t ppe_solve(ppe_plan_t plan, const double* rho0, const double* dt,
  * memory, and before enqueuing further sweeps the call waits for the copy
  * made 4 sweeps earlier (so it blocks the host while at most 4 more sweeps
  * are queued).  With tol = 0 it only enqueues, like ppe_solve.
- * ppe_correct(pn = p, pnm1 = p, p) then applies the variable-density
+ * ppe_correct(rho0 = NULL, pn = p, pnm1 = p, p) then applies the variable-density
  * projection u^{n+1} = u* - dt G p / rho_f, whose relative divergence error
  * is the last res. */
 ppe_status_t ppe_solve_varcoef(ppe_plan_t plan, const double* rho0, const double* dt,
@@ -288,14 +304,17 @@ typedef struct ppe_ring_s* ppe_ring_t;
 ppe_status_t ppe_ring_create(ppe_plan_t plan, const double* const* pn, const double* const* pnm1, ppe_ring_t* out);
 
 /* One projection step: ppe_solve + ppe_correct with the ring's history, then
- * rotate (the new pressure becomes p^n).  Arguments as for those calls.
+ * rotate (the new pressure becomes p^n).  Arguments as for those calls
+ * (ppe_correct with rho0 = NULL: it reads the solve's info record).
  * split_defect: NULL, or a device array [batch][2] that receives the relative
  * residual of the variable-coefficient problem, Eq. (25), for p_hat ([b][0])
  * and for the split pressure p^{n+1} ([b][1]) -- how far the split is from
- * the variable-density projection this step (Sec. 5.4).  It needs the plan's
- * FP64 residual buffer (PPE_FLAG_VARCOEF) and takes the
- * pressure from one sweep of ppe_solve_varcoef (equal to ppe_solve's to
- * rounding). */
+ * the variable-density projection this step (Sec. 5.4).  Both residuals are
+ * formed in FP64, relative to ||(rho0/dt)(D u* - S_c)||_2, after ppe_solve:
+ * the pressure, velocities and info record are bitwise those of the step
+ * without the diagnostic, in either precision (a mixed plan's pressure is
+ * the refined one).  It needs the plan's FP64 residual buffer
+ * (PPE_FLAG_VARCOEF; else PPE_ERR_ARG). */
 ppe_status_t ppe_ring_step(ppe_ring_t ring, const double* rho0, const double* dt,
                            const double* const* us, const double* const* vs, const double* const* ws,
                            const double* const* rho, const double* const* S,
@@ -316,13 +335,25 @@ int64_t ppe_ring_steps(ppe_ring_t ring);
 /* Free the ring's buffers (waits for the plan's stream first). */
 ppe_status_t ppe_ring_destroy(ppe_ring_t ring);
 
-/* Projection, Eq. (28) (Sec. 5.4), and the continuity check of the result.
- * Reads rho0_used and compat_defect from `info` (as written by ppe_solve for
- * the same inputs) and writes div_l2, div_max, div0_l2, res_rel and status
- * (PPE_ERR_NOT_CONVERGED when res_rel > desc.tol > 0).
+/* Projection, Eq. (28) (Sec. 5.4), with rho0 of Eq. (27), and the continuity
+ * check of the result.
+ *   rho0    : NULL, or a host array of `batch` values.
+ *             NULL: rho0_used and compat_defect are read from `info`, as
+ *             ppe_solve wrote them for the same inputs (the usual step).
+ *             Array: > 0 is used as given, <= 0 requests min(rho) (device);
+ *             the compatibility defect mean(D u* - S) (zero-flux ends; 0 with
+ *             an outflow top) is reduced from us, vs, ws, S here, and `info`
+ *             is initialised (status 0, iters 0, rho0_used, compat_defect).
+ *             This projects with a pressure obtained elsewhere: no ppe_solve
+ *             needs to precede the call.
+ *   dt      : host array, > 0
+ *   p       : the pressure to project with (any source)
  *   u, v, w : host arrays of `batch` device pointers (outputs; the wall rows
- *             of v are copied from v*, an outflow row is corrected). */
-ppe_status_t ppe_correct(ppe_plan_t plan, const double* dt,
+ *             of v are copied from v*, an outflow row is corrected)
+ * Writes div_l2, div_max, div0_l2, res_rel, p_mean and status
+ * (PPE_ERR_NOT_CONVERGED when res_rel > desc.tol > 0 on a mixed plan,
+ * PPE_ERR_NONFINITE for a non-finite residual) to `info`. */
+ppe_status_t ppe_correct(ppe_plan_t plan, const double* rho0, const double* dt,
                          const double* const* us, const double* const* vs, const double* const* ws,
                          const double* const* rho, const double* const* pn, const double* const* pnm1,
                          const double* const* p, const double* const* S,

@@ -53,7 +53,7 @@ INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("rho0_used", "<f8")
 assert INFO_DTYPE.itemsize == 64
 
 EXPORTS = ["ppe_plan_workspace_bytes", "ppe_plan", "ppe_plan_destroy", "ppe_plan_set_stream", "ppe_solve",
-           "ppe_correct", "ppe_residual", "ppe_source", "ppe_predict", "ppe_solve_varcoef", "ppe_ring_create",
+           "ppe_rhs", "ppe_correct", "ppe_residual", "ppe_source", "ppe_predict", "ppe_solve_varcoef", "ppe_ring_create",
            "ppe_ring_step",
            "ppe_ring_pressure", "ppe_ring_read", "ppe_ring_steps", "ppe_ring_destroy", "ppe_plan_profile",
            "ppe_plan_profile_read", "ppe_version"]
@@ -111,7 +111,9 @@ def load(path: str = LIB_PATH):
     lib.ppe_plan_set_stream.restype = ctypes.c_int
     lib.ppe_solve.argtypes = [P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, P]
     lib.ppe_solve.restype = ctypes.c_int
-    lib.ppe_correct.argtypes = [P, D, PP, PP, PP, PP, PP, PP, PP, PP, PP, PP, PP, P]
+    lib.ppe_rhs.argtypes = [P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, P]
+    lib.ppe_rhs.restype = ctypes.c_int
+    lib.ppe_correct.argtypes = [P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, PP, PP, PP, P]
     lib.ppe_correct.restype = ctypes.c_int
     lib.ppe_residual.argtypes = [P, PP, PP, PP, PP, P]
     lib.ppe_residual.restype = ctypes.c_int
@@ -260,7 +262,11 @@ class Plan:
         return [self._field(t, shape, name, i) for i, t in enumerate(seq)]
 
     def new_info(self):
-        return self._torch.zeros(self.batch * 8, dtype=self._torch.float64, device=self.device)
+        """Zeroed info records, allocated and cleared on the plan's stream (the
+        library writes them on that stream, so the fill is ordered before)."""
+        torch = self._torch
+        with torch.cuda.stream(self.stream):
+            return torch.zeros(self.batch * 8, dtype=torch.float64, device=self.device)
 
     # -- entry points -------------------------------------------------------
     def solve(self, rho0: Sequence[float], dt: Sequence[float], us, vs, ws, rho, pn, pnm1, S, p, info=None):
@@ -276,6 +282,21 @@ class Plan:
         st = self.lib.ppe_solve(self._h, _dbl(rho0), _dbl(dt), *[_ptrs(a) for a in args],
                                 ctypes.c_void_p(info.data_ptr()))
         _check(st, "ppe_solve")
+        return info
+
+    def rhs(self, rho0: Sequence[float], dt: Sequence[float], us, vs, ws, rho, pn, pnm1, S, b, info=None):
+        """ppe_rhs: the right-hand side of Eq. (29) into the tensors b; returns info."""
+        if info is None:
+            info = self.new_info()
+        B = self.batch
+        if len(rho0) != B or len(dt) != B:
+            raise PPEError("rho0 and dt need one value per instance")
+        args = [self._batch(us, "us"), self._batch(vs, "vs", v=True), self._batch(ws, "ws"),
+                self._batch(rho, "rho"), self._batch(pn, "pn"), self._batch(pnm1, "pnm1"), self._batch(S, "S"),
+                self._batch(b, "b")]
+        st = self.lib.ppe_rhs(self._h, _dbl(rho0), _dbl(dt), *[_ptrs(a) for a in args],
+                              ctypes.c_void_p(info.data_ptr()))
+        _check(st, "ppe_rhs")
         return info
 
     def solve_varcoef(self, rho0: Sequence[float], dt: Sequence[float], us, vs, ws, rho, pn, pnm1, S, p,
@@ -301,12 +322,26 @@ class Plan:
         _check(st, "ppe_solve_varcoef")
         return info, hist
 
-    def correct(self, dt: Sequence[float], us, vs, ws, rho, pn, pnm1, p, S, u, v, w, info):
-        """ppe_correct: writes u, v, w and the continuity fields of `info`."""
+    def correct(self, dt: Sequence[float], us, vs, ws, rho, pn, pnm1, p, S, u, v, w, info=None, rho0=None):
+        """ppe_correct: writes u, v, w and the continuity fields of `info`.
+
+        rho0=None projects with the rho0 and compatibility defect that
+        ppe_solve left in `info`; a sequence of per-instance values (<= 0:
+        min(rho)) projects a pressure from anywhere, and `info` is then
+        initialised by the call (allocated here when None)."""
+        if info is None:
+            if rho0 is None:
+                raise PPEError("correct: without rho0 the info records of the solve are needed")
+            info = self.new_info()
+        if rho0 is not None and len(rho0) != self.batch:
+            raise PPEError("rho0 needs one value per instance")
+        if len(dt) != self.batch:
+            raise PPEError("dt needs one value per instance")
         args = [self._batch(us, "us"), self._batch(vs, "vs", v=True), self._batch(ws, "ws"),
                 self._batch(rho, "rho"), self._batch(pn, "pn"), self._batch(pnm1, "pnm1"), self._batch(p, "p"),
                 self._batch(S, "S"), self._batch(u, "u"), self._batch(v, "v", v=True), self._batch(w, "w")]
-        st = self.lib.ppe_correct(self._h, _dbl(dt), *[_ptrs(a) for a in args], ctypes.c_void_p(info.data_ptr()))
+        st = self.lib.ppe_correct(self._h, _dbl(rho0) if rho0 is not None else None, _dbl(dt),
+                                  *[_ptrs(a) for a in args], ctypes.c_void_p(info.data_ptr()))
         _check(st, "ppe_correct")
         return info
 
@@ -446,8 +481,10 @@ def step(plan: Plan, fields: List[Dict], rho0, dt, outputs: Optional[List[Dict]]
     """solve + correct for a batch of field dicts; returns (outputs, info tensor)."""
     torch = plan._torch
     if outputs is None:
-        outputs = [{"p": torch.empty_like(f["rho"]), "u": torch.empty_like(f["us"]),
-                    "v": torch.empty_like(f["vs"]), "w": torch.empty_like(f["ws"])} for f in fields]
+        # allocated on the plan's stream, which writes them
+        with torch.cuda.stream(plan.stream):
+            outputs = [{"p": torch.empty_like(f["rho"]), "u": torch.empty_like(f["us"]),
+                        "v": torch.empty_like(f["vs"]), "w": torch.empty_like(f["ws"])} for f in fields]
     g = lambda k: [f[k] for f in fields]
     o = lambda k: [x[k] for x in outputs]
     info = plan.solve(rho0, dt, g("us"), g("vs"), g("ws"), g("rho"), g("pn"), g("pnm1"), g("S"), o("p"), info)

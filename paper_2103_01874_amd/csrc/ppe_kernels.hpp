@@ -3,8 +3,10 @@
 //
 // Pass structure of one solve (every pass is one launch over all instances
 // of a batch; blockIdx.z is the instance):
-//   k_assemble   b = (rho0/dt)(D u* - S) + D(beta_f G p_hat)  (Eq. 29) fused
-//                with the real FFT along x (two rows packed per complex FFT)
+//   k_rhs        b = (rho0/dt)(D u* - S) + D(beta_f G p_hat)  (Eq. 29), a
+//                z-marching stencil; writes b and the block sums of D u* - S
+//   k_r2c        real FFT along x of b (two rows packed per complex FFT) into
+//                the half spectrum, with the FP64 row sums (zero mode)
 //   k_fft_z      complex FFT along z, in place on the half spectrum
 //   k_tri        one tridiagonal system in y per (kx, kz), partition method;
 //                the (0,0) system is solved in FP64 from FP64 plane sums
@@ -12,7 +14,8 @@
 //                pinned and gauge-fixed)
 //   k_fft_z      inverse
 //   k_c2r        inverse real FFT along x -> p (or p update when refining)
-//   k_residual   FP64 r = b - L p fused with the real FFT of r (refinement)
+//   k_resid      FP64 r = b - L p, stored in the spectrum's precision
+//                (refinement), then k_r2c .. k_c2r again on r
 //   k_correct    u^{n+1} = u* - dt[G p/rho0 + gamma_f G p_hat]  (Eq. 28) and
 //                the continuity residual of the result
 // and, before a solve when the caller assembles S through the library:

@@ -646,14 +646,14 @@ ppe_status_t varcoef_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb
     }
     if (it == 0)
       PPE_TIMED(p, "k_resid_var",
-                PPE_PPT_SWITCH(p->mres.ppt, (k_resid_var<TS, PPT, true><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
+                PPE_PPT_SWITCH(p->mres.ppt, (k_resid_var<TS, PPT, 1><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
                                                                          march_lds(p->mres, 2), p->stream>>>(
-                                                tab, g, p->mres.m, W, p->r64))));
+                                                tab, g, p->mres.m, W, p->r64, 1))));
     else
       PPE_TIMED(p, "k_resid_var",
-                PPE_PPT_SWITCH(p->mres.ppt, (k_resid_var<TS, PPT, false><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
+                PPE_PPT_SWITCH(p->mres.ppt, (k_resid_var<TS, PPT, 0><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
                                                                           march_lds(p->mres, 2), p->stream>>>(
-                                                tab, g, p->mres.m, W, p->r64))));
+                                                tab, g, p->mres.m, W, p->r64, 1))));
     finish(p, tab, inst0, nb, p->mres.grid, it == max_iters ? FIN_RESID_LAST : FIN_RESID, 1, 0.0,
            h0 ? h0 + it : nullptr, hs);
     if (it == max_iters) break;
@@ -665,6 +665,31 @@ ppe_status_t varcoef_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb
     PPE_TIMED(p, "k_c2r",
               PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1))));
   }
+  return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
+}
+
+// Split defect of a projection step (Sec. 5.4): the relative residual of the
+// variable-coefficient problem, Eq. (25), for p_hat (out[2 b]) and for the
+// split pressure p^{n+1} that ppe_solve left in tab.p (out[2 b + 1]), both in
+// FP64.  Runs after that solve, on its scalars (rho0, the stop scale and the
+// mean of the right-hand side); c = (rho0/dt)(D u* - S) replaces b in b64.
+template <typename TS>
+ppe_status_t defect_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb, double* out) {
+  Work<TS> W = make_work<TS>(p, inst0);
+  PPE_TIMED(p, "k_rhs",
+            PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT, false><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads,
+                                                               march_lds(p->mrhs, 1), p->stream>>>(tab, p->g,
+                                                                                                   p->mrhs.m, W))));
+  PPE_TIMED(p, "k_resid_var",
+            PPE_PPT_SWITCH(p->mres.ppt, (k_resid_var<TS, PPT, 2><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
+                                                                   march_lds(p->mres, 2), p->stream>>>(
+                                            tab, p->g, p->mres.m, W, p->r64, 0))));
+  finish(p, tab, inst0, nb, p->mres.grid, FIN_DEFECT, 0, 0.0, out + 2 * (size_t)inst0, 2);
+  PPE_TIMED(p, "k_resid_var",
+            PPE_PPT_SWITCH(p->mres.ppt, (k_resid_var<TS, PPT, 0><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
+                                                                   march_lds(p->mres, 2), p->stream>>>(
+                                            tab, p->g, p->mres.m, W, p->r64, 0))));
+  finish(p, tab, inst0, nb, p->mres.grid, FIN_DEFECT, 0, 0.0, out + 2 * (size_t)inst0 + 1, 2);
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
 }
 
@@ -856,6 +881,53 @@ ppe_status_t ppe_solve(ppe_plan_t p, const double* rho0, const double* dt, const
   return PPE_OK;
 }
 
+ppe_status_t ppe_rhs(ppe_plan_t p, const double* rho0, const double* dt, const double* const* us,
+                     const double* const* vs, const double* const* ws, const double* const* rho,
+                     const double* const* pn, const double* const* pnm1, const double* const* S, double* const* b,
+                     ppe_info_t* info) {
+  if (!p || !rho0 || !dt || !info) return PPE_ERR_ARG;
+  const int B = p->d.batch;
+  if (!ptrs_ok((const void* const*)us, B) || !ptrs_ok((const void* const*)vs, B) ||
+      !ptrs_ok((const void* const*)ws, B) || !ptrs_ok((const void* const*)rho, B) ||
+      !ptrs_ok((const void* const*)pn, B) || !ptrs_ok((const void* const*)pnm1, B) ||
+      !ptrs_ok((const void* const*)S, B) || !ptrs_ok((const void* const*)b, B))
+    return PPE_ERR_ARG;
+  for (int i = 0; i < B; ++i)
+    if (!(dt[i] > 0) || !std::isfinite(dt[i]) || std::isnan(rho0[i])) return PPE_ERR_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
+  const Geom& g = p->g;
+  for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
+    const int nb = std::min(kMaxLaunch, B - i0);
+    PtrTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    for (int i = 0; i < nb; ++i) {
+      InstPtrs& q = tab.in[i];
+      q.us = us[i0 + i];
+      q.vs = vs[i0 + i];
+      q.ws = ws[i0 + i];
+      q.rho = rho[i0 + i];
+      q.pn = pn[i0 + i];
+      q.pnm1 = pnm1[i0 + i];
+      q.S = S[i0 + i];
+      q.info = info + i0 + i;
+      q.rho0_in = rho0[i0 + i];
+      q.dt = dt[i0 + i];
+    }
+    rho_min_pass(p, tab, i0, nb);
+    Work<double> W = make_work<double>(p, i0);
+    PPE_TIMED(p, "k_rhs",
+              PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<double, PPT, true><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads,
+                                                                    march_lds(p->mrhs, 2), p->stream>>>(
+                                               tab, g, p->mrhs.m, W))));
+    finish(p, tab, i0, nb, p->mrhs.grid, FIN_RHS, 0);
+    for (int i = 0; i < nb; ++i)
+      if (hipMemcpyAsync(b[i0 + i], p->b64 + (size_t)(i0 + i) * g.npts, (size_t)g.npts * sizeof(double),
+                         hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+        return PPE_ERR_DEVICE;
+  }
+  return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
+}
+
 ppe_status_t ppe_solve_varcoef(ppe_plan_t p, const double* rho0, const double* dt, const double* const* us,
                                const double* const* vs, const double* const* ws, const double* const* rho,
                                const double* const* pn, const double* const* pnm1, const double* const* S,
@@ -901,10 +973,11 @@ ppe_status_t ppe_solve_varcoef(ppe_plan_t p, const double* rho0, const double* d
   return PPE_OK;
 }
 
-ppe_status_t ppe_correct(ppe_plan_t p, const double* dt, const double* const* us, const double* const* vs,
-                         const double* const* ws, const double* const* rho, const double* const* pn,
-                         const double* const* pnm1, const double* const* pin, const double* const* S,
-                         double* const* u, double* const* v, double* const* w, ppe_info_t* info) {
+ppe_status_t ppe_correct(ppe_plan_t p, const double* rho0, const double* dt, const double* const* us,
+                         const double* const* vs, const double* const* ws, const double* const* rho,
+                         const double* const* pn, const double* const* pnm1, const double* const* pin,
+                         const double* const* S, double* const* u, double* const* v, double* const* w,
+                         ppe_info_t* info) {
   if (!p || !dt || !info) return PPE_ERR_ARG;
   const int B = p->d.batch;
   if (!ptrs_ok((const void* const*)us, B) || !ptrs_ok((const void* const*)vs, B) ||
@@ -914,12 +987,35 @@ ppe_status_t ppe_correct(ppe_plan_t p, const double* dt, const double* const* us
       !ptrs_ok((const void* const*)u, B) || !ptrs_ok((const void* const*)v, B) || !ptrs_ok((const void* const*)w, B))
     return PPE_ERR_ARG;
   for (int i = 0; i < B; ++i)
-    if (!(dt[i] > 0) || !std::isfinite(dt[i])) return PPE_ERR_ARG;
+    if (!(dt[i] > 0) || !std::isfinite(dt[i]) || (rho0 && std::isnan(rho0[i]))) return PPE_ERR_ARG;
   if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
   const Geom& g = p->g;
   const double tol = p->d.precision == PPE_PREC_MIXED ? p->d.tol : 0.0;
   for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
     const int nb = std::min(kMaxLaunch, B - i0);
+    if (rho0) {
+      // the caller's rho0 (Eq. 27): min(rho) where asked, and the
+      // compatibility defect mean(D u* - S) into a fresh info record
+      PtrTable it;
+      std::memset(&it, 0, sizeof(it));
+      for (int i = 0; i < nb; ++i) {
+        InstPtrs& q = it.in[i];
+        q.u = const_cast<double*>(us[i0 + i]);
+        q.v = const_cast<double*>(vs[i0 + i]);
+        q.w = const_cast<double*>(ws[i0 + i]);
+        q.S = S[i0 + i];
+        q.rho = rho[i0 + i];
+        q.info = info + i0 + i;
+        q.rho0_in = rho0[i0 + i];
+        q.dt = dt[i0 + i];
+      }
+      rho_min_pass(p, it, i0, nb);
+      const long long blocks = std::min<long long>((g.npts + 255) / 256, kRedBlocks);
+      PPE_TIMED(p, "k_div_stats",
+                (k_div_stats<<<dim3((unsigned)blocks, 1, nb), 256, 0, p->stream>>>(it, g, p->partial, p->pstride,
+                                                                                    nullptr, i0, 0)));
+      finish(p, it, i0, nb, (int)blocks, FIN_CORR_INIT, 0);
+    }
     PtrTable tab;
     std::memset(&tab, 0, sizeof(tab));
     for (int i = 0; i < nb; ++i) {
@@ -1095,11 +1191,34 @@ ppe_status_t ppe_ring_step(ppe_ring_t r, const double* rho0, const double* dt, c
     pm[i] = r->buf[r->prev] + i * n;
     pp[i] = r->buf[next] + i * n;
   }
-  ppe_status_t st = split_defect ? ppe_solve_varcoef(p, rho0, dt, us, vs, ws, rho, pn, pm, S, pp, info, 1, 0.0,
-                                                     split_defect)
-                                 : ppe_solve(p, rho0, dt, us, vs, ws, rho, pn, pm, S, pp, info);
+  if (split_defect && (!p->r64 || p->r64_elem != 8)) return PPE_ERR_ARG;  // needs PPE_FLAG_VARCOEF
+  ppe_status_t st = ppe_solve(p, rho0, dt, us, vs, ws, rho, pn, pm, S, pp, info);
   if (st != PPE_OK) return st;
-  st = ppe_correct(p, dt, us, vs, ws, rho, pn, pm, pp, S, u, v, w, info);
+  if (split_defect) {
+    for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
+      const int nb = std::min(kMaxLaunch, B - i0);
+      PtrTable tab;
+      std::memset(&tab, 0, sizeof(tab));
+      for (int i = 0; i < nb; ++i) {
+        InstPtrs& q = tab.in[i];
+        q.us = us[i0 + i];
+        q.vs = vs[i0 + i];
+        q.ws = ws[i0 + i];
+        q.rho = rho[i0 + i];
+        q.pn = pn[i0 + i];
+        q.pnm1 = pm[i0 + i];
+        q.S = S[i0 + i];
+        q.p = pp[i0 + i];
+        q.info = info + i0 + i;
+        q.rho0_in = rho0[i0 + i];
+        q.dt = dt[i0 + i];
+      }
+      st = p->d.precision == PPE_PREC_FP64 ? defect_typed<double>(p, tab, i0, nb, split_defect)
+                                           : defect_typed<float>(p, tab, i0, nb, split_defect);
+      if (st != PPE_OK) return st;
+    }
+  }
+  st = ppe_correct(p, nullptr, dt, us, vs, ws, rho, pn, pm, pp, S, u, v, w, info);
   if (st != PPE_OK) return st;
   r->prev = r->cur;
   r->cur = next;

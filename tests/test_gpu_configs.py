@@ -1,0 +1,185 @@
+"""GPU parity at the benchmark configurations' own shapes (Sec. 5.4, Eqs. 27-29).
+
+* Every grid of the batched and serving mixes (32^3, 64^3, 96x64x96,
+  128x64x128, 192x96x192, 256x128x256), one two-phase sheet each, in the FP64
+  direct solve and in FP32 spectra with one FP64 refinement sweep (the launch
+  configuration the benchmark times), against the FP64 oracle, every point,
+  in l2 and pointwise (parity_util.check).
+* The 48-instance uneven mix exactly as the benchmark launches it: one plan
+  per shape group, groups on four streams; each of the 48 results against its
+  own oracle solve, in both precisions.
+* ppe_correct with the caller's rho0 and a pressure from elsewhere (no
+  ppe_solve before it), against the oracle's projection of the same pressure.
+* ppe_rhs: the right-hand side of Eq. (29) against the oracle's assembly, to
+  the rounding of the formula itself.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import parity_util as PU
+from paper_2103_01874_amd import binding, synth
+from paper_2103_01874_amd.serve import GpuBackend, Request, group_by_shape
+
+pytestmark = pytest.mark.gpu
+
+FP64, MIXED = binding.PPE_PREC_FP64, binding.PPE_PREC_MIXED
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def run_single(pr, precision, max_refine):
+    torch = _torch()
+    plan = binding.Plan(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, precision=precision, tol=1e-12,
+                        max_refine=max_refine, ybc=pr.ybc)
+    f = binding.to_device(pr)
+    outs, info = binding.step(plan, [f], [pr.rho0], [pr.dt])
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in outs[0].items()}
+    rec = binding.decode_info(info)[0]
+    plan.close()
+    return got, rec
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+@pytest.mark.parametrize("shape", synth.SERVE_SHAPES)
+def test_config_shape_against_oracle(shape, precision):
+    """One sheet of the uneven mix's recipe (rho ratio U(3,12), thickness
+    U(0.15,0.45), three interface modes) per grid of the mixes."""
+    pr = synth.mixed_instance(9100 + sum(shape), shape=shape)
+    got, rec = run_single(pr, precision, 0 if precision == FP64 else 1)
+    PU.check(pr, got, rec, PU.oracle_step(pr), label="fp64 " if precision == FP64 else "mixed ")
+    if precision == MIXED:
+        assert rec["iters"] == 1
+
+
+def test_batch_48_each_instance_against_oracle():
+    """The 48 uneven instances in both precisions, launched as the benchmark
+    launches them, each against its own oracle solve."""
+    torch = _torch()
+    probs = synth.batch_48()
+    dev = torch.device("cuda", 0)
+    results = {}
+    for precision in (FP64, MIXED):
+        be = GpuBackend(n_slots=4, precision=precision, tol=1e-12, max_refine=1)
+        reqs = [Request(rid=i, shape=(p.nx, p.ny, p.nz), inputs=binding.to_device(p, dev), rho0=p.rho0, dt=p.dt,
+                        arrival=0.0) for i, p in enumerate(probs)]
+        groups = group_by_shape(reqs, binding.MAX_BATCH)
+        plans = [be.make_plan(i % 4, g[0].shape, len(g), g[0].lengths) for i, g in enumerate(groups)]
+        outs, infos = [], []
+        for i, (pl, g) in enumerate(zip(plans, groups)):
+            with torch.cuda.stream(be.streams[i % 4]):
+                o, inf = binding.step(pl, [r.inputs for r in g], [r.rho0 for r in g], [r.dt for r in g])
+            outs.append(o)
+            infos.append(inf)
+        torch.cuda.synchronize()
+        for g, o, inf in zip(groups, outs, infos):
+            for r, oo, rec in zip(g, o, binding.decode_info(inf)):
+                results[(precision, r.rid)] = ({k: v.cpu().numpy() for k, v in oo.items()}, rec)
+        for pl in plans:
+            pl.close()
+        del reqs, outs, infos
+    print(f"groups: {[(g[0].shape, len(g)) for g in groups]}", flush=True)
+    for i, pr in enumerate(probs):
+        ref = PU.oracle_step(pr)
+        for precision in (FP64, MIXED):
+            got, rec = results.pop((precision, i))
+            PU.check(pr, got, rec, ref, label=f"#{i} {'fp64' if precision == FP64 else 'mixed'} ")
+
+
+@pytest.mark.parametrize("ybc", [0, 1])
+def test_correct_with_callers_rho0_and_pressure(ybc):
+    """No ppe_solve first: the projection of the oracle's own pressure, and of
+    an arbitrary pressure (p^n), with rho0 given and with rho0 = min(rho),
+    against the oracle's projection of the same pressure."""
+    torch = _torch()
+    pr = (synth.sheet_problem(48, 24, 32, seed=41, nmodes=3) if ybc == 0
+          else synth.jet_problem(48, 24, 32, seed=42, nmodes=3))
+    g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=ybc)
+    ref = PU.oracle_step(pr)
+    plan = binding.Plan(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=ybc)
+    f = binding.to_device(pr)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    cases = [("oracle p", ref["p"], pr.rho0, pr.rho0), ("p^n", pr.pn, pr.rho0, pr.rho0),
+             ("p^n, rho0 = min", pr.pn, -1.0, float(pr.rho.min()))]
+    for name, p_in, r0_arg, r0 in cases:
+        u, v, w = (torch.empty_like(f[k]) for k in ("us", "vs", "ws"))
+        info = plan.correct([pr.dt], [f["us"]], [f["vs"]], [f["ws"]], [f["rho"]], [f["pn"]], [f["pnm1"]],
+                            [dev(p_in)], [f["S"]], [u], [v], [w], rho0=[r0_arg])
+        torch.cuda.synchronize()
+        rec = binding.decode_info(info)[0]
+        uo, vo, wo = O.correct(g, r0, pr.dt, pr.us, pr.vs, pr.ws, pr.rho, pr.pn, pr.pnm1, p_in)
+        chk = O.divergence_check(g, pr.us, pr.vs, pr.ws, pr.S, uo, vo, wo)
+        e = {}
+        for k, got, want, st in (("u", u, uo, pr.us), ("v", v, vo, pr.vs), ("w", w, wo, pr.ws)):
+            a = got.cpu().numpy()
+            e[k] = PU.rel(a - st, want - st)
+            e["inf_" + k] = PU.rel_inf(a - st, want - st)
+        print(f"ybc={ybc} {name}: {e} rho0={rec['rho0_used']} compat={rec['compat_defect']:.3e} "
+              f"(oracle {chk['compat']:.3e}) eps_div={rec['res_rel']:.3e} (oracle {chk['rel']:.3e})", flush=True)
+        assert rec["status"] == 0 and rec["iters"] == 0
+        assert rec["rho0_used"] == r0
+        assert all(e[k] <= 1e-12 for k in ("u", "v", "w")), e
+        assert all(e["inf_" + k] <= 1e-11 for k in ("u", "v", "w")), e
+        scale = abs(chk["compat"]) + chk["div0_l2"] / np.sqrt(pr.npts)
+        assert abs(rec["compat_defect"] - chk["compat"]) <= 1e-13 * scale
+        assert abs(rec["div0_l2"] - chk["div0_l2"]) <= 1e-12 * chk["div0_l2"]
+        # the projection of the solution is solenoidal up to S_c; of p^n it is not
+        if name == "oracle p":
+            assert rec["res_rel"] <= 1e-12
+        else:
+            assert abs(rec["res_rel"] - chk["rel"]) <= 1e-10 * chk["rel"]
+    plan.close()
+
+
+def assembly_bound(pr, rho0):
+    """Forward error bound of any FP64 evaluation of Eq. (29) at each cell:
+    32 eps times the same sums with every operand replaced by its absolute
+    value.  The pressure differences are bounded through q = 2|p^n| + |p^{n-1}|
+    (the rounding of a difference of nearly equal values scales with the
+    values, not with the difference); |beta_f| <= 1.  Generous at the y ends
+    (the neighbours are replicated), which only loosens the bound there."""
+    g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=pr.ybc)
+    c0 = rho0 / pr.dt
+    au, av, aw = np.abs(pr.us), np.abs(pr.vs), np.abs(pr.ws)
+    vel = ((au + np.roll(au, -1, axis=2)) / g.dx + (av[:, :-1, :] + av[:, 1:, :]) / g.dy
+           + (aw + np.roll(aw, -1, axis=0)) / g.dz + np.abs(pr.S))
+    q = 2.0 * np.abs(pr.pn) + np.abs(pr.pnm1)
+    qp = np.concatenate([q[:, :1, :], q, q[:, -1:, :]], axis=1)
+    lap = ((np.roll(q, 1, axis=2) + 2 * q + np.roll(q, -1, axis=2)) / g.dx ** 2
+           + (qp[:, :-2, :] + 2 * q + qp[:, 2:, :]) / g.dy ** 2
+           + (np.roll(q, 1, axis=0) + 2 * q + np.roll(q, -1, axis=0)) / g.dz ** 2)
+    return 32 * np.finfo(float).eps * (c0 * vel + lap)
+
+
+@pytest.mark.parametrize("ybc", [0, 1])
+@pytest.mark.parametrize("shape", [(32, 16, 24), (96, 64, 96)])
+def test_rhs_pass_against_oracle_assembly(shape, ybc):
+    """b of ppe_rhs against the oracle's assemble_rhs: within the assembly's
+    own FP64 forward error bound at every cell, and 1e-15 relative in l2."""
+    torch = _torch()
+    pr = (synth.sheet_problem(*shape, seed=51, nmodes=3) if ybc == 0 else synth.jet_problem(*shape, seed=52))
+    plan = binding.Plan(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=ybc)
+    f = binding.to_device(pr)
+    b = torch.empty_like(f["rho"])
+    info = plan.rhs([pr.rho0], [pr.dt], [f["us"]], [f["vs"]], [f["ws"]], [f["rho"]], [f["pn"]], [f["pnm1"]],
+                    [f["S"]], [b])
+    torch.cuda.synchronize()
+    rec = binding.decode_info(info)[0]
+    g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=ybc)
+    bo = O.assemble_rhs(g, pr.rho0, pr.dt, pr.us, pr.vs, pr.ws, pr.rho, pr.pn, pr.pnm1, pr.S)
+    got = b.cpu().numpy()
+    bound = assembly_bound(pr, pr.rho0)
+    l2 = PU.rel(got, bo)
+    worst = float((np.abs(got - bo) / bound).max())
+    print(f"ybc={ybc} {shape}: b l2 rel {l2:.2e}, max |b - b_o| / bound {worst:.3f}", flush=True)
+    assert np.all(np.abs(got - bo) <= bound)
+    assert l2 <= 1e-15
+    assert rec["rho0_used"] == pr.rho0
+    d0 = O.divergence(g, pr.us, pr.vs, pr.ws) - pr.S
+    want = float(d0.mean()) if ybc == 0 else 0.0
+    assert abs(rec["compat_defect"] - want) <= 1e-13 * (abs(want) + np.sqrt(np.mean(d0 * d0)))
+    plan.close()

@@ -5,6 +5,8 @@ projection step is specified to), measured as
   eps_p  = ||p - p_o|| / ||p_o||              (both zero-mean)
   eps_du = ||(u - u*) - (u_o - u*)|| / ||u_o - u*||   (the correction itself)
   eps_div = ||D u - S_c|| / ||D u* - S_c||     (from the library's own check)
+and pointwise: max|p - p_o| <= 1e-12 max|p_o|, and for each velocity
+component max|du - du_o| <= 1e-11 max|du_o| (parity_util.check).
 The FP64 path is expected near 1e-14; the mixed path must reach 1e-12 after
 refinement.  Where the problem's own FP64 conditioning puts 1e-12 out of
 reach of any solver (random fields at ny ~ 2048, pressures dominated by a mode
@@ -16,11 +18,12 @@ import numpy as np
 import pytest
 
 import oracle as O
+import parity_util as PU
 from paper_2103_01874_amd import binding, synth
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-12
+TOL = PU.TOL
 
 
 def _torch():
@@ -43,39 +46,9 @@ def gpu_step(problems, precision=binding.PPE_PREC_FP64, tol=1e-12, max_refine=2,
     return res, recs
 
 
-def oracle_step(pr, rho0=None, method="spectral"):
-    g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=pr.ybc)
-    return O.ppe_step(g, pr.rho0 if rho0 is None else rho0, pr.dt, *pr.fields(), method=method)
-
-
-def errors(pr, got, ref):
-    rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
-    du = np.concatenate([(got[k] - getattr(pr, s)).ravel() for k, s in (("u", "us"), ("v", "vs"), ("w", "ws"))])
-    duo = np.concatenate([(ref[k] - getattr(pr, s)).ravel() for k, s in (("u", "us"), ("v", "vs"), ("w", "ws"))])
-    return {"eps_p": rel(got["p"], ref["p"]), "eps_du": rel(du, duo)}
-
-
-def check(pr, got, rec, ref, tol=TOL, tol_p=None, tol_du=None, tol_div=None):
-    e = errors(pr, got, ref)
-    print(f"[{pr.nx}x{pr.ny}x{pr.nz}] eps_p={e['eps_p']:.2e} eps_du={e['eps_du']:.2e} "
-          f"eps_div={rec['res_rel']:.2e} iters={rec['iters']} status={rec['status']}", flush=True)
-    assert rec["status"] == 0, rec
-    assert e["eps_p"] <= (tol if tol_p is None else tol_p), e
-    assert e["eps_du"] <= (tol if tol_du is None else tol_du), e
-    assert rec["res_rel"] <= (tol if tol_div is None else tol_div), rec
-    assert abs(rec["rho0_used"] - ref["rho0"]) <= 1e-15 * ref["rho0"]
-    # v on the walls is copied, never corrected
-    assert np.array_equal(got["v"][:, 0, :], pr.vs[:, 0, :])
-    if pr.ybc == 0:
-        assert abs(rec["p_mean"]) <= 1e-13 * np.abs(ref["p"]).max()
-        assert np.array_equal(got["v"][:, -1, :], pr.vs[:, -1, :])
-        scale = abs(ref["compat"]) + ref["div0_l2"] / np.sqrt(pr.npts)
-        assert abs(rec["compat_defect"] - ref["compat"]) <= 1e-13 * scale
-    else:
-        # outflow top: nothing removed, no gauge, top face corrected
-        assert rec["compat_defect"] == 0.0
-        assert abs(rec["p_mean"] - ref["p"].mean()) <= 1e-12 * np.abs(ref["p"]).max()
-        assert not np.array_equal(got["v"][:, -1, :], pr.vs[:, -1, :])
+oracle_step = PU.oracle_step
+errors = PU.errors
+check = PU.check
 
 
 TINY = [(6, 4, 6), (12, 5, 9), (8, 3, 4), (4, 2, 3), (9, 7, 12), (1, 4, 8), (8, 4, 1), (32, 16, 24),
@@ -261,6 +234,24 @@ def gradient_sensitivity(pr, ref):
     return float(np.linalg.norm(a - b) / np.linalg.norm(a))
 
 
+def gradient_rounding_bound(pr, ref, ulps=16):
+    """Pointwise form of the same effect: a pressure in error by `ulps` units
+    in the last place of max|p| at each point (the forward error of an FFT
+    solve, about log2(nx nz) + a few roundings per value) moves each face
+    gradient by up to 2 ulps spacing(max|p|)/h; relative to the component's
+    largest gradient, the largest over the components whose oracle gradient
+    is not identically zero."""
+    g = O.Grid(pr.nx, pr.ny, pr.nz, pr.lx, pr.ly, pr.lz, ybc=pr.ybc)
+    p = ref["p"]
+    dp = ulps * np.spacing(np.abs(p).max())
+    out = 0.0
+    for gc, h in zip(O.gradient(g, p), (g.dx, g.dy, g.dz)):
+        m = np.abs(gc).max()
+        if m > 0:
+            out = max(out, 2.0 * dp / h / m)
+    return out
+
+
 @pytest.mark.parametrize("ybc", [0, 1])
 def test_y_refine_flag_on_a_wide_domain(ybc):
     """PPE_FLAG_Y_REFINE at ny = 64: the zero-flux kx = 1 systems have their
@@ -270,7 +261,8 @@ def test_y_refine_flag_on_a_wide_domain(ybc):
     divergence is held as in the smooth-mode test above: at s ~ 6e-8 its FP64
     value carries ~1e-9 in any solver.  p is nearly constant in y there, and
     one ulp of p moves the correction by 8e-13 relative: the correction is
-    held to twice that figure (at least 1e-12)."""
+    held to twice that figure (at least 1e-12); pointwise, each component to
+    what 16 ulps of max|p| at every point put through G (at least 1e-11)."""
     pr = wide_domain_problem(ybc)
     ref = oracle_step(pr)
     (plain,), (rec0,) = gpu_step([pr])
@@ -278,8 +270,11 @@ def test_y_refine_flag_on_a_wide_domain(ybc):
     (got,), (rec,) = gpu_step([pr], flags=binding.PPE_FLAG_Y_REFINE)
     own = oracle_divergence(pr, ref)
     gsens = gradient_sensitivity(pr, ref)
-    print(f"oracle's own eps_div: {own:.2e}; one-ulp sensitivity of G p: {gsens:.2e}", flush=True)
-    check(pr, got, rec, ref, tol_du=max(TOL, 2.0 * gsens), tol_div=max(TOL, 4.0 * own))
+    ginf = gradient_rounding_bound(pr, ref)
+    print(f"oracle's own eps_div: {own:.2e}; one-ulp sensitivity of G p: {gsens:.2e}; "
+          f"pointwise gradient bound {ginf:.2e}", flush=True)
+    check(pr, got, rec, ref, tol_du=max(TOL, 2.0 * gsens), tol_div=max(TOL, 4.0 * own),
+          tol_inf_du=max(10 * TOL, ginf))
 
 
 def test_sheet_512x256x512_full_oracle_fp64_and_mixed():
