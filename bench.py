@@ -63,7 +63,9 @@ WORKLOADS = {
                                          "same-shape instances batched per launch"),
     "serve_fp64": ("serve", 0, 0, "the serve_mixed request stream through the FP64 direct solve"),
     "serve_mixed": ("serve", 1, 1, "Poisson-arrival stream of sheets over {32^3 .. 256x128x256}, FP32 spectra + "
-                                   "FP64 refinement to 1e-12, 64 GB HBM budget, plans cached, continuous "
+                                   "FP64 refinement to 1e-12, each request's inputs copied into memory of its own "
+                                   "at admission, inputs + outputs + plans admitted against a 64 GB HBM budget, "
+                                   "plans cached, continuous "
                                    "batching on 4 streams"),
 }
 
@@ -298,10 +300,13 @@ def run_serve(args, precision, max_refine, desc, n_requests=500):
              for _ in range(n_requests)]
 
     def requests(arrivals):
+        # every request gets device inputs of its own, copied from the pool at
+        # admission and charged against the budget until it completes
         out = []
         for i, ((shape, k), a) in enumerate(zip(picks, arrivals)):
             pr, f = pool[shape][k]
-            out.append(Request(rid=i, shape=shape, inputs=f, rho0=pr.rho0, dt=pr.dt, arrival=float(a)))
+            out.append(Request(rid=i, shape=shape, inputs=None, source=f, rho0=pr.rho0, dt=pr.dt,
+                               arrival=float(a)))
         return out
 
     be = GpuBackend(n_slots=4, precision=precision, tol=1e-12, max_refine=max_refine)
@@ -333,7 +338,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sheet_256x128x256_fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="sheet_512x256x512_fp64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed roofline pass")
     ap.add_argument("--max-points", type=int, default=256 * 128 * 256,

@@ -2,9 +2,11 @@
 
 Requests (one projection step each: ppe_solve + ppe_correct) arrive over
 time.  The scheduler
-  * admits a request when its memory (output fields, plus the workspace of a
-    plan it would need that is not cached yet) fits the HBM budget, rejecting
-    a request that could never fit (PPE_ERR_NOMEM);
+  * admits a request when its memory (its seven resident input fields and
+    four output fields, plus the workspace of a plan it would need that is
+    not cached yet) fits the HBM budget, rejecting a request that could never
+    fit (PPE_ERR_NOMEM); an admitted request's inputs are made resident then
+    (Backend.stage) and released when it completes;
   * keeps plans cached per (stream slot, shape, batch size), evicting unused
     plans least-recently-used when the budget is tight;
   * whenever a stream slot is free, launches the oldest ready request together
@@ -37,7 +39,7 @@ Shape = Tuple[int, int, int]
 class Request:
     rid: int
     shape: Shape                   # (nx, ny, nz)
-    inputs: object                 # backend-specific handle to the seven input fields
+    inputs: object                 # backend-specific handle to the seven resident input fields
     rho0: float
     dt: float
     arrival: float                 # seconds on the server clock
@@ -51,6 +53,10 @@ class Request:
     info: Optional[dict] = None
     outputs: object = None
     group: Optional[int] = None    # launch group id
+    # where the inputs come from when they are not resident yet: the backend
+    # copies them into request-owned device memory at admission (None: the
+    # caller's `inputs` are used as they are)
+    source: object = None
 
     @property
     def npts(self) -> int:
@@ -80,6 +86,18 @@ class Backend:
 
     def output_bytes(self, shape: Shape) -> int:
         raise NotImplementedError
+
+    def input_bytes(self, shape: Shape) -> int:
+        """Device bytes of a request's inputs: u*, w*, rho, p^n, p^{n-1}, S on
+        cells and v* on the ny + 1 v faces, float64 (the interface's layouts)."""
+        nx, ny, nz = shape
+        return 8 * (6 * nx * ny * nz + nx * (ny + 1) * nz)
+
+    def stage(self, req: "Request") -> None:
+        """Make an admitted request's inputs resident (default: they are)."""
+
+    def release(self, req: "Request") -> None:
+        """Free what stage() allocated for a request that has completed."""
 
     def plan_bytes(self, shape: Shape, batch: int) -> int:
         raise NotImplementedError
@@ -142,8 +160,12 @@ class Server:
             self.used -= nbytes
         return self.used + need <= self.budget
 
+    def _bytes(self, req: Request) -> int:
+        """Memory a request holds from admission to completion: inputs and outputs."""
+        return self.b.output_bytes(req.shape) + self.b.input_bytes(req.shape)
+
     def _admit(self, req: Request) -> bool:
-        need = self.b.output_bytes(req.shape)
+        need = self._bytes(req)
         worst = need + self.b.plan_bytes(req.shape, 1)
         if worst > self.budget:
             req.status = PPE_ERR_NOMEM
@@ -154,6 +176,7 @@ class Server:
             return False
         self.used += need
         req.admitted = self.clock()
+        self.b.stage(req)
         self.ready.append(req)
         return True
 
@@ -196,7 +219,8 @@ class Server:
                     self.ready.popleft()
                     head.status = PPE_ERR_NOMEM
                     head.done = self.clock()
-                    self.used -= self.b.output_bytes(head.shape)
+                    self.used -= self._bytes(head)
+                    self.b.release(head)
                     self.rejected.append(head)
                     continue
                 # no room for the plan now: retry once requests complete
@@ -219,7 +243,8 @@ class Server:
             self.b.collect(handle, group)
             for r in group:
                 r.done = now
-                self.used -= self.b.output_bytes(r.shape)
+                self.used -= self._bytes(r)
+                self.b.release(r)
                 self.finished.append(r)
             self.plan_busy[key] = False
             del self.inflight[slot]
@@ -300,6 +325,7 @@ class GpuBackend(Backend):
         self.binding = binding
         self.device = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(self.device) for _ in range(n_slots)]
+        self.stage_stream = torch.cuda.Stream(self.device)  # input copies at admission
         self.precision, self.tol, self.max_refine = precision, tol, max_refine
         self.keep_outputs = keep_outputs
         self._ws: Dict[Tuple[Shape, int], int] = {}
@@ -316,6 +342,23 @@ class GpuBackend(Backend):
             self._ws[key] = self.binding.workspace_bytes(d)
         return self._ws[key]
 
+    def stage(self, req):
+        """Copy the request's source fields into device memory it owns (on
+        the staging stream; its launch waits for the copy)."""
+        if req.source is None or req.inputs is not None:
+            return
+        torch = self.torch
+        with torch.cuda.stream(self.stage_stream):
+            req.inputs = {k: v.clone() for k, v in req.source.items()}
+            ev = torch.cuda.Event()
+            ev.record(self.stage_stream)
+        req.staged = ev
+
+    def release(self, req):
+        if req.source is not None:
+            req.inputs = None
+            req.staged = None
+
     def make_plan(self, slot, shape, batch, lengths, ybc=0):
         nx, ny, nz = shape
         return self.binding.Plan(nx, ny, nz, *lengths, precision=self.precision, tol=self.tol,
@@ -327,6 +370,12 @@ class GpuBackend(Backend):
     def launch(self, slot, plan, reqs):
         torch = self.torch
         st = self.streams[slot]
+        for r in reqs:
+            ev = getattr(r, "staged", None)
+            if ev is not None:
+                st.wait_event(ev)
+                for t in r.inputs.values():  # allocated on the staging stream, used on this one
+                    t.record_stream(st)
         with torch.cuda.stream(st):
             fields = [r.inputs for r in reqs]
             outs = []

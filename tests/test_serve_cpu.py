@@ -34,6 +34,14 @@ class FakeBackend(Backend):
         self.freed = []
         self.launches = []
         self.bad = set(bad)
+        self.staged = []
+        self.released = []
+
+    def stage(self, req):
+        self.staged.append(req.rid)
+
+    def release(self, req):
+        self.released.append(req.rid)
 
     def output_bytes(self, shape):
         nx, ny, nz = shape
@@ -105,11 +113,15 @@ def test_fifo_head_goes_first():
     assert be.launches[1][1] == [1]
 
 
+def request_bytes(shape):
+    be = FakeBackend(FakeClock())
+    return be.output_bytes(shape) + be.input_bytes(shape)
+
+
 def test_budget_limits_admission_and_rejects_impossible():
     big = (256, 128, 256)
     small = (32, 32, 32)
-    ob = FakeBackend(FakeClock()).output_bytes
-    budget = ob(small) * 3 + 10**5
+    budget = request_bytes(small) * 3 + 10**5
     reqs = [mk(0, big, 0.0)] + [mk(1 + i, small, 0.0) for i in range(6)]
     srv, be, m = run(reqs, budget=budget, slots=1, plan_cost=10)
     assert reqs[0].status == PPE_ERR_NOMEM
@@ -123,10 +135,9 @@ def test_plan_cache_reuses_and_evicts():
     srv, be, m = run(reqs, slots=1)
     # requests arrive one by one and finish before the next: one plan reused
     assert len(be.made) == 1
-    ob = FakeBackend(FakeClock()).output_bytes
     shapes = [(32, 32, 32), (64, 32, 32), (32, 64, 32)]
     reqs = [mk(i, shapes[i % 3], 0.01 * i) for i in range(6)]
-    budget = max(ob(s) for s in shapes) + 1500  # room for one plan at a time
+    budget = max(request_bytes(s) for s in shapes) + 1500  # room for one plan at a time
     srv, be, m = run(reqs, budget=budget, slots=1, plan_cost=1000)
     assert m["served"] == 6
     assert len(be.freed) >= 4  # plans evicted to make room
@@ -191,3 +202,40 @@ def test_points_cap_limits_large_groups_only():
     reqs3 = [mk(i, (128, 64, 128), 0.0) for i in range(4)] + [mk(4, (32, 32, 32), 0.0)]
     _, _, whole = run(reqs3, slots=1)
     assert capped["mean_ms"] < whole["mean_ms"]
+
+
+def test_input_fields_are_charged_at_admission():
+    """The seven resident input fields (6 cell fields and v* on ny + 1 faces)
+    count against the budget: a budget that holds a request's four outputs
+    and its plan but not its inputs rejects it with PPE_ERR_NOMEM."""
+    shape = (64, 32, 48)
+    be = FakeBackend(FakeClock())
+    nx, ny, nz = shape
+    assert be.input_bytes(shape) == 8 * (6 * nx * ny * nz + nx * (ny + 1) * nz)
+    assert be.input_bytes(shape) > be.output_bytes(shape)
+    budget = be.output_bytes(shape) + be.input_bytes(shape) // 2 + 10 * 1000
+    reqs = [mk(0, shape, 0.0)]
+    srv, be, m = run(reqs, budget=budget, slots=1, plan_cost=1000)
+    assert reqs[0].status == PPE_ERR_NOMEM and m["served"] == 0
+    assert be.staged == [] and be.launches == []
+    # with room for the inputs too it is served, staged once and released once
+    reqs = [mk(0, shape, 0.0)]
+    srv, be, m = run(reqs, budget=request_bytes(shape) + 1000, slots=1, plan_cost=1000)
+    assert reqs[0].status == 0 and m["served"] == 1
+    assert be.staged == [0] and be.released == [0]
+    assert srv.used == 1000  # only the cached plan is left
+
+
+def test_inputs_limit_how_many_requests_are_resident():
+    """Eight equal requests, a budget for three requests' inputs and outputs
+    (and their plans): at most three are admitted at a time, every request
+    is released exactly once, and the memory in use returns to the plans."""
+    shape = (32, 32, 32)
+    budget = 3 * request_bytes(shape) + 4 * 1000
+    reqs = [mk(i, shape, 0.0) for i in range(8)]
+    srv, be, m = run(reqs, budget=budget, slots=2, plan_cost=1000)
+    assert m["served"] == 8 and m["rejected"] == 0
+    assert sorted(be.staged) == list(range(8)) and sorted(be.released) == list(range(8))
+    assert sum(len(ids) for _, ids in be.launches) == 8
+    assert max(len(ids) for _, ids in be.launches) <= 2
+    assert srv.used == sum(nbytes for _, nbytes in srv.plans.values())
