@@ -404,6 +404,33 @@ typedef struct {
  * The result is the S that ppe_solve and ppe_correct take. */
 ppe_status_t ppe_source(ppe_plan_t plan, const ppe_source_t* src, double* const* S);
 
+/* Pressure solve without a plan and without allocating, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The same computation as
+ * ppe_plan(desc) + ppe_solve and, when u, v, w are given, ppe_correct with
+ * rho0 = NULL; results equal theirs to rounding (the twiddle and eigenvalue
+ * tables are formed on the device here, on the host by ppe_plan).
+ *   desc   : as for ppe_plan; ny <= 256, and neither PPE_FLAG_Y_REFINE nor
+ *            PPE_FLAG_VARCOEF (else PPE_ERR_UNSUPPORTED)
+ *   stream : hipStream_t the work is enqueued on (NULL = the null stream)
+ *   rho0 .. S, p, info : as for ppe_solve
+ *   u, v, w : NULL (pressure only), or host arrays of `batch` device pointers
+ *            receiving the projection, as for ppe_correct
+ * Workspace: a 64 MiB array in the library's device data, one per GPU, held
+ * until the process ends; its device address is looked up on the first call
+ * on each device.  A descriptor whose workspace (ppe_plan_workspace_bytes)
+ * exceeds it returns PPE_ERR_NOMEM and enqueues nothing: FP64 grids up to
+ * about 3.5 M cells in all (192x96x192 fits).  The call allocates no memory.
+ * Every call on one GPU uses that GPU's array and leaves its contents behind
+ * (the call clears what it relies on): calls that overlap on one GPU, on
+ * different streams or from different threads, race and give wrong results;
+ * serialise them (one stream, or events). */
+ppe_status_t ppe_solve_noalloc(const ppe_desc_t* desc, void* stream, const double* rho0, const double* dt,
+                               const double* const* us, const double* const* vs, const double* const* ws,
+                               const double* const* rho, const double* const* pn, const double* const* pnm1,
+                               const double* const* S, double* const* p, double* const* u, double* const* v,
+                               double* const* w, ppe_info_t* info);
+
 /* Per-kernel timing, for measurement tools.  With profiling enabled every
  * launch the plan makes is bracketed by two HIP events on the plan's stream;
  * durations are folded into per-kernel totals.  Enabling clears the totals.

@@ -25,7 +25,9 @@ PPE_FLAG_VARCOEF = 1
 PPE_FLAG_Y_REFINE = 2
 PPE_OK = 0
 PPE_ERR_ARG = -1
+PPE_ERR_NOMEM = -2
 PPE_ERR_NOT_CONVERGED = -4
+PPE_ERR_UNSUPPORTED = -6
 MAX_BATCH = 64
 
 STATUS = {0: "ok", -1: "bad argument", -2: "out of memory", -3: "device error", -4: "not converged",
@@ -56,7 +58,7 @@ EXPORTS = ["ppe_plan_workspace_bytes", "ppe_plan", "ppe_plan_destroy", "ppe_plan
            "ppe_rhs", "ppe_correct", "ppe_residual", "ppe_source", "ppe_predict", "ppe_solve_varcoef", "ppe_ring_create",
            "ppe_ring_step",
            "ppe_ring_pressure", "ppe_ring_read", "ppe_ring_steps", "ppe_ring_destroy", "ppe_plan_profile",
-           "ppe_plan_profile_read", "ppe_version"]
+           "ppe_plan_profile_read", "ppe_version", "ppe_solve_noalloc"]
 
 SOURCE_FIELDS = ("C", "div_g", "div_l", "mdot", "area", "rho_g", "rho_l")
 
@@ -113,6 +115,8 @@ def load(path: str = LIB_PATH):
     lib.ppe_solve.restype = ctypes.c_int
     lib.ppe_rhs.argtypes = [P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, P]
     lib.ppe_rhs.restype = ctypes.c_int
+    lib.ppe_solve_noalloc.argtypes = [ctypes.POINTER(Desc), P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, PP, PP, PP, P]
+    lib.ppe_solve_noalloc.restype = ctypes.c_int
     lib.ppe_correct.argtypes = [P, D, D, PP, PP, PP, PP, PP, PP, PP, PP, PP, PP, PP, P]
     lib.ppe_correct.restype = ctypes.c_int
     lib.ppe_residual.argtypes = [P, PP, PP, PP, PP, P]
@@ -491,3 +495,38 @@ def step(plan: Plan, fields: List[Dict], rho0, dt, outputs: Optional[List[Dict]]
     plan.correct(dt, g("us"), g("vs"), g("ws"), g("rho"), g("pn"), g("pnm1"), o("p"), g("S"), o("u"), o("v"),
                  o("w"), info)
     return outputs, info
+
+
+def solve_noalloc(nx, ny, nz, fields: List[Dict], rho0, dt, outputs: List[Dict], info, lx=2 * np.pi, ly=2.0,
+                  lz=2 * np.pi, precision=PPE_PREC_FP64, tol=1e-12, max_refine=1, ybc=PPE_YBC_WALLS, stream=None,
+                  project=True):
+    """ppe_solve_noalloc: a whole batch solved (and projected, with `project`)
+    in the library's static device workspace, with no plan; `outputs` holds
+    preallocated p (and u, v, w) tensors, `info` a preallocated record tensor.
+    Returns the ppe_status_t code (PPE_ERR_NOMEM when the grid exceeds the
+    static workspace) rather than raising, so callers can fall back."""
+    import torch
+
+    desc = make_desc(nx, ny, nz, lx, ly, lz, precision, tol, max_refine, len(fields), ybc, 0)
+    dev = outputs[0]["p"].device
+    shape_c, shape_v = (nz, ny, nx), (nz, ny + 1, nx)
+
+    def chk(t, shape, name):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or tuple(t.shape) != shape \
+                or t.device != dev or not t.is_contiguous():
+            raise PPEError(f"{name}: expected contiguous float64 {shape} on {dev}")
+        return t
+
+    g = lambda k, shape: _ptrs([chk(f[k], shape, k) for f in fields])
+    o = lambda k, shape: _ptrs([chk(x[k], shape, k) for x in outputs])
+    if len(rho0) != len(fields) or len(dt) != len(fields) or len(outputs) != len(fields):
+        raise PPEError("one rho0, dt and output record per instance")
+    if info.numel() < 8 * len(fields) or info.dtype != torch.float64 or info.device != dev:
+        raise PPEError("info: expected float64 records on the fields' device")
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    uvw = (o("u", shape_c), o("v", shape_v), o("w", shape_c)) if project else (None, None, None)
+    lib = load()
+    return int(lib.ppe_solve_noalloc(ctypes.byref(desc), ctypes.c_void_p(s.cuda_stream), _dbl(rho0), _dbl(dt),
+                                     g("us", shape_c), g("vs", shape_v), g("ws", shape_c), g("rho", shape_c),
+                                     g("pn", shape_c), g("pnm1", shape_c), g("S", shape_c), o("p", shape_c), *uvw,
+                                     ctypes.c_void_p(info.data_ptr())))

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -742,6 +743,67 @@ hipError_t allow_big_lds(int bytes) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Workspace for callers that cannot allocate: one file-scope device array per
+// GPU, held until the process ends.  Host code never uses the array's name as
+// an address: its device address comes from hipGetSymbolAddress, looked up
+// once per device with that device current, and is what kernels receive.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;  // 64 MiB per GPU
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Device address of `scratch` on device `dev` (the current device), looked up
+// and the large-LDS kernel attributes set on the first call for that device.
+void* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return g_scratch_ptr[dev];
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+  int lds_max = 65536;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return nullptr;
+  if (lds_max > 65536 && allow_big_lds(lds_max) != hipSuccess) return nullptr;
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+
+// Twiddle tables exp(-2 pi i t / n) and the eigenvalue tables of the periodic
+// directions, on the device (sinpi / sincospi in FP64; exact values where the
+// circle meets the axes), for a workspace built without host copies.
+__global__ __launch_bounds__(256) void k_tables(double* twx, int nx, double* twz, int nz, double* lamx, int hx,
+                                                double* lamz, double dx, double dz) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const auto tw = [](double* w, int n, int q) {
+    double s, c;
+    sincospi(2.0 * q / n, &s, &c);
+    if ((4LL * q) % n == 0) {
+      const int qq = (int)((4LL * q / n) % 4);
+      c = qq == 0 ? 1.0 : (qq == 2 ? -1.0 : 0.0);
+      s = qq == 1 ? 1.0 : (qq == 3 ? -1.0 : 0.0);
+    }
+    w[2 * q] = c;
+    w[2 * q + 1] = -s;
+  };
+  if (t < nx) tw(twx, nx, t);
+  if (t < nz) tw(twz, nz, t);
+  if (t < hx) {
+    const double s = sinpi((double)t / nx);
+    lamx[t] = -4.0 / (dx * dx) * s * s;
+  }
+  if (t < nz) {
+    const double s = sinpi((double)t / nz);
+    lamz[t] = -4.0 / (dz * dz) * s * s;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1312,6 +1374,90 @@ ppe_status_t ppe_predict(ppe_plan_t p, const ppe_predict_t* in, double* const* u
     PPE_TIMED(p, "k_predict_w", (k_predict<2><<<dim3(blocks, 1, nb), 256, 0, p->stream>>>(tab, g)));
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
+}
+
+ppe_status_t ppe_solve_noalloc(const ppe_desc_t* desc, void* stream, const double* rho0, const double* dt,
+                               const double* const* us, const double* const* vs, const double* const* ws,
+                               const double* const* rho, const double* const* pn, const double* const* pnm1,
+                               const double* const* S, double* const* p, double* const* u, double* const* v,
+                               double* const* w, ppe_info_t* info) {
+  if (!desc_ok(desc)) return PPE_ERR_ARG;
+  if (!u != !v || !u != !w) return PPE_ERR_ARG;
+  // every host-checkable argument before anything is enqueued
+  {
+    const int nb = desc->batch;
+    if (!rho0 || !dt || !info) return PPE_ERR_ARG;
+    if (!ptrs_ok((const void* const*)us, nb) || !ptrs_ok((const void* const*)vs, nb) ||
+        !ptrs_ok((const void* const*)ws, nb) || !ptrs_ok((const void* const*)rho, nb) ||
+        !ptrs_ok((const void* const*)pn, nb) || !ptrs_ok((const void* const*)pnm1, nb) ||
+        !ptrs_ok((const void* const*)S, nb) || !ptrs_ok((const void* const*)p, nb))
+      return PPE_ERR_ARG;
+    if (u && (!ptrs_ok((const void* const*)u, nb) || !ptrs_ok((const void* const*)v, nb) ||
+              !ptrs_ok((const void* const*)w, nb)))
+      return PPE_ERR_ARG;
+    for (int i = 0; i < nb; ++i)
+      if (!(dt[i] > 0) || !std::isfinite(dt[i]) || std::isnan(rho0[i])) return PPE_ERR_ARG;
+  }
+  // the refined y solve needs a block list built on the host, and the
+  // fixed-point buffer is for ppe_solve_varcoef: neither is offered here
+  if (desc->ny > 256 || (desc->flags & (PPE_FLAG_Y_REFINE | PPE_FLAG_VARCOEF)) != 0) return PPE_ERR_UNSUPPORTED;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PPE_ERR_DEVICE;
+  ppe_plan_s P;  // (a plan on the stack: no allocation; its pointers go into `scratch`)
+  P.d = *desc;
+  P.stream = reinterpret_cast<hipStream_t>(stream);
+  P.device = dev;
+  int lds_max = 65536;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return PPE_ERR_DEVICE;
+  if (!shape_plan(&P, (size_t)std::max(lds_max, 65536))) return PPE_ERR_UNSUPPORTED;
+  const ppe_desc_t& d = P.d;
+  const size_t B = (size_t)d.batch;
+  const auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
+  const size_t sz[] = {B * (size_t)P.g.spec_elems * spec_elem_bytes(&d),  // spectrum
+                       B * (size_t)P.g.npts * 8,                         // b64
+                       B * (size_t)P.g.npts * r64_elem_bytes(d),         // refinement residual
+                       B * (size_t)d.ny * d.nz * 8,                      // row sums
+                       B * (size_t)d.ny * 8,                             // plane sums
+                       B * (size_t)kNScal * 8,                           // scalars
+                       B * (size_t)P.pstride * 8,                        // partials
+                       (size_t)P.g.hx * 8, (size_t)d.nz * 8,            // lam_x, lam_z
+                       (size_t)2 * d.nx * 8, (size_t)2 * d.nz * 8};      // twiddles
+  size_t need = 0;
+  for (size_t x : sz) need += al(std::max<size_t>(x, 8));
+  if (need > kScratchBytes) return PPE_ERR_NOMEM;  // larger than the static workspace
+  char* base = static_cast<char*>(scratch_on(dev));
+  if (!base) return PPE_ERR_DEVICE;
+  void* parts[11];
+  size_t off = 0;
+  for (int i = 0; i < 11; ++i) {
+    parts[i] = base + off;
+    off += al(std::max<size_t>(sz[i], 8));
+  }
+  P.spec = parts[0];
+  P.b64 = static_cast<double*>(parts[1]);
+  P.r64_elem = r64_elem_bytes(d);
+  P.r64 = P.r64_elem > 0 ? static_cast<double*>(parts[2]) : nullptr;
+  P.rowsum = static_cast<double*>(parts[3]);
+  P.colsum = static_cast<double*>(parts[4]);
+  P.scal = static_cast<double*>(parts[5]);
+  P.partial = static_cast<double*>(parts[6]);
+  P.lamx = static_cast<double*>(parts[7]);
+  P.lamz = static_cast<double*>(parts[8]);
+  P.fx.tw = static_cast<double*>(parts[9]);
+  P.fz.tw = static_cast<double*>(parts[10]);
+  if (hipSetDevice(dev) != hipSuccess) return PPE_ERR_DEVICE;
+  // tables for this shape, and the per-instance scalars cleared (the array
+  // keeps whatever the previous call on this GPU left)
+  const int nt = std::max(std::max(d.nx, d.nz), P.g.hx);
+  k_tables<<<(nt + 255) / 256, 256, 0, P.stream>>>(P.fx.tw, d.nx, P.fz.tw, d.nz, P.lamx, P.g.hx, P.lamz, P.g.dx,
+                                                   P.g.dz);
+  const long long nsc = (long long)B * kNScal;
+  k_fill<<<(unsigned)((nsc + 255) / 256), 256, 0, P.stream>>>(P.scal, nsc, 0.0);
+  if (hipGetLastError() != hipSuccess) return PPE_ERR_DEVICE;
+  ppe_status_t st = ppe_solve(&P, rho0, dt, us, vs, ws, rho, pn, pnm1, S, p, info);
+  if (st != PPE_OK || !u) return st;
+  return ppe_correct(&P, nullptr, dt, us, vs, ws, rho, pn, pnm1, p, S, u, v, w, info);
 }
 
 ppe_status_t ppe_plan_profile(ppe_plan_t p, int32_t enable) {

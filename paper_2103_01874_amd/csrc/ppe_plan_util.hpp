@@ -34,22 +34,25 @@ inline bool fft_factor(int n, HostFft& f) {
   while (m % 2 == 0) { m /= 2; ++a; }
   while (m % 3 == 0) { m /= 3; ++b; }
   if (m != 1) return false;
-  std::vector<int> r(b, 3);
+  // (a fixed array: planning allocates no memory)
+  int r[kMaxStages + 16];
+  int nr = 0;
+  for (int q = 0; q < b; ++q) r[nr++] = 3;
   if (b == 0) {
-    while (a >= 3) { r.push_back(8); a -= 3; }
-    if (a == 2) r.push_back(4);
-    else if (a == 1) r.push_back(2);
+    while (a >= 3) { r[nr++] = 8; a -= 3; }
+    if (a == 2) r[nr++] = 4;
+    else if (a == 1) r[nr++] = 2;
   } else {
-    while (a >= 2) { r.push_back(4); a -= 2; }
-    if (a == 1) r.push_back(2);
+    while (a >= 2) { r[nr++] = 4; a -= 2; }
+    if (a == 1) r[nr++] = 2;
   }
-  if ((int)r.size() > kMaxStages) return false;
+  if (nr > kMaxStages) return false;
   int e = 1;
-  for (int x : r) e = e / gcd_i(e, x) * x;
+  for (int q = 0; q < nr; ++q) e = e / gcd_i(e, r[q]) * r[q];
   f.n = n;
   f.e = e;
   f.tc = n / e;
-  f.nst = (int)r.size();
+  f.nst = nr;
   int ns = 1;
   for (int s = 0; s < f.nst; ++s) {
     f.radix[s] = r[s];
