@@ -15,6 +15,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <numeric>
 #include <new>
 #include <string>
 #include <vector>
@@ -67,6 +68,7 @@ struct ppe_plan_s {
   int mc = 16;           // register rows per chunk (template of k_tri)
   int fx_ct = 0, fz_ct = 0;  // power-of-two lengths run with compile-time FFT plans (0: run-time plan)
   bool tri_refine = false;  // one difference-form refinement step in the y solve
+  int spec_chunks = 1;   // kx chunks the spectral chain runs in (see launch_chain)
   int src_pt = 8;        // units per thread of k_source (2, 4 or 8)
   int src_vec = 2;       // cells per unit of k_source (1, or 2 when aligned)
   size_t lds_x = 0, lds_z = 0, lds_t = 0;
@@ -75,6 +77,7 @@ struct ppe_plan_s {
     March m;
     int grid = 0;    // blocks per instance
     int ppt = 1;     // interior points per thread per plane (kernel template)
+    int nt = 256;    // threads per block (kernel template: 256, 512 or 1024)
     int tslots = 0;  // LDS slots of a tile plane with its halo ring
   } mrhs, mcor, mres;
   double* r64 = nullptr;   // refinement / fixed-point residual (mixed, or PPE_FLAG_VARCOEF)
@@ -138,12 +141,14 @@ size_t spec_elem_bytes(const ppe_desc_t* d) {
   return d->precision == PPE_PREC_FP64 ? 2 * sizeof(double) : 2 * sizeof(float);
 }
 
-// Tile of a marching stencil kernel: TXT = nx when nx <= 128, else the
-// largest divisor of nx up to 128; TJ rows so that a tile plane has about
-// `points` interior cells; KC planes per chunk so that an instance gets about
-// 2048 blocks.
-bool march_shape(const ppe_desc_t& d, int points, int max_txt, const char* env, ppe_plan_s::MarchCfg& c) {
+// Tile of a marching stencil kernel run by `nt` threads per block: TXT = nx
+// when nx <= max_txt, else the largest divisor of nx up to max_txt; TJ rows so
+// that a tile plane has about `points` interior cells; KC planes per chunk so
+// that an instance gets about 2048 blocks.
+bool march_shape(const ppe_desc_t& d, int points, int max_txt, const char* env, ppe_plan_s::MarchCfg& c,
+                 int nt = kMarchThreads) {
   March& M = c.m;
+  c.nt = nt;
   if (tune_env("PPE_TUNE_TXT") > 0) max_txt = tune_env("PPE_TUNE_TXT");
   M.txt = d.nx;
   if (M.txt > max_txt) {
@@ -156,8 +161,8 @@ bool march_shape(const ppe_desc_t& d, int points, int max_txt, const char* env, 
   }
   M.tj = std::max(1, std::min(points / M.txt, d.ny));
   if (tune_env(env) > 0) M.tj = std::max(1, std::min(tune_env(env), d.ny));
-  while (M.tj > 1 && 2 * M.txt + 2 * M.tj > kRingPT * kMarchThreads) --M.tj;
-  if ((long long)M.tj * M.txt > kMarchThreads * kMaxPPT) return false;
+  while (M.tj > 1 && 2 * M.txt + 2 * M.tj > kRingPT * nt) --M.tj;
+  if ((long long)M.tj * M.txt > (long long)nt * kMaxPPT) return false;
   M.ntx = d.nx / M.txt;
   M.ntj = (d.ny + M.tj - 1) / M.tj;
   const int target = tune_env("PPE_TUNE_MARCH_BLOCKS") > 0 ? tune_env("PPE_TUNE_MARCH_BLOCKS") : 2048;
@@ -165,7 +170,8 @@ bool march_shape(const ppe_desc_t& d, int points, int max_txt, const char* env, 
   // and at most 16 planes per block: with fewer, longer marches the final
   // set of resident blocks leaves the GPU idle for longer (512x256x512:
   // 128 planes per block, k_correct 1387 us; 16 planes, 1306 us)
-  nkc = std::max(nkc, (d.nz + 15) / 16);
+  const int max_planes = tune_env("PPE_TUNE_MAX_PLANES") > 0 ? tune_env("PPE_TUNE_MAX_PLANES") : 16;
+  nkc = std::max(nkc, (d.nz + max_planes - 1) / max_planes);
   nkc = std::min(nkc, std::max(1, d.nz / 2));
   M.kc = (d.nz + nkc - 1) / nkc;
   M.nkc = (d.nz + M.kc - 1) / M.kc;
@@ -174,7 +180,7 @@ bool march_shape(const ppe_desc_t& d, int points, int max_txt, const char* env, 
   c.grid = 8 * M.per_xcd;
   const int npt = M.txt * M.tj;
   c.ppt = 1;
-  while (c.ppt * kMarchThreads < npt) c.ppt *= 2;
+  while (c.ppt * nt < npt) c.ppt *= 2;
   c.tslots = (M.txt + 2) * (M.tj + 2);
   return true;
 }
@@ -250,6 +256,16 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   p->tri_refine = d.ny > 256 || (d.flags & PPE_FLAG_Y_REFINE) != 0;
   p->lds_t = std::max((size_t)p->txs * 2 * P * sizeof(RedRow<double>), (size_t)p->txs * P * 8);
   if (p->lds_x > 65536 || p->lds_z > lds_limit || p->lds_t > 65536) return false;
+  // spectral-chain chunks of at most 192 MiB of spectrum (all instances), so
+  // that a chunk stays in the 256 MB last-level cache through its z FFT,
+  // tridiagonal and inverse z passes with room for the other streams
+  // (512x256x512 FP64: 539 MB in 3 chunks, step 3.41 -> 3.22 ms; FP32
+  // spectra there: 2 chunks; grids whose spectrum fits run unchunked)
+  {
+    const double spec_bytes = (double)d.batch * (double)g.spec_elems * (double)spec_elem_bytes(&d);
+    p->spec_chunks = std::max(1, (int)std::ceil(spec_bytes / (192.0 * 1048576.0)));
+  }
+  if (tune_env("PPE_TUNE_SPEC_CHUNKS") > 0) p->spec_chunks = tune_env("PPE_TUNE_SPEC_CHUNKS");
   // target-divergence pass
   if (tune_env("PPE_TUNE_SRC_PT") > 0) p->src_pt = tune_env("PPE_TUNE_SRC_PT");
   if (tune_env("PPE_TUNE_SRC_VEC") > 0) p->src_vec = tune_env("PPE_TUNE_SRC_VEC");
@@ -257,7 +273,15 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   if (p->src_vec != 1) p->src_vec = 2;
   // z-marching stencils: TXT x TJ tiles (TXT a divisor of nx, <= 128), KC planes
   // per chunk; the tile height per kernel trades halo traffic against registers
-  if (!march_shape(d, 256, 64, "PPE_TUNE_TJ_RHS", p->mrhs) || !march_shape(d, 256, 64, "PPE_TUNE_TJ_COR", p->mcor) ||
+  // threads per block of the two big stencils (512 and 1024 hold taller
+  // tiles at one point per thread: fewer halo rows fetched per interior row)
+  const auto nt_of = [](const char* env, int def) {
+    const int v = tune_env(env);
+    return (v == 256 || v == 512 || v == 1024) ? v : def;
+  };
+  const int nt_rhs = nt_of("PPE_TUNE_NT_RHS", kMarchThreads), nt_cor = nt_of("PPE_TUNE_NT_COR", kMarchThreads);
+  if (!march_shape(d, nt_rhs == kMarchThreads ? 256 : nt_rhs, 64, "PPE_TUNE_TJ_RHS", p->mrhs, nt_rhs) ||
+      !march_shape(d, nt_cor == kMarchThreads ? 256 : nt_cor, 64, "PPE_TUNE_TJ_COR", p->mcor, nt_cor) ||
       !march_shape(d, 256, 64, "PPE_TUNE_TJ_RES", p->mres))
     return false;
   if ((size_t)3 * p->mcor.tslots * 8 > 65536) return false;
@@ -374,7 +398,7 @@ void free_plan(ppe_plan_s* p) {
 // LDS of a marching kernel holding `fields` row arrays (at least the block's
 // reduction scratch, which reuses the same memory after the march)
 size_t march_lds(const ppe_plan_s::MarchCfg& c, int fields) {
-  return (size_t)std::max(fields * c.tslots, kMarchThreads) * 8;
+  return (size_t)std::max(fields * c.tslots, c.nt) * 8;
 }
 
 template <typename TS>
@@ -402,6 +426,19 @@ Work<TS> make_work(ppe_plan_s* p, int inst0) {
     case 2: { constexpr int PPT = 2; CALL; } break; \
     case 4: { constexpr int PPT = 4; CALL; } break; \
     default: return PPE_ERR_UNSUPPORTED;            \
+  }
+
+// Launch CALL with PPT and NT the marching kernel's points per thread and
+// threads per block of launch shape CFG.
+#define PPE_MARCH_SWITCH(CFG, CALL)                                                  \
+  switch ((CFG).nt * 8 + (CFG).ppt) {                                               \
+    case 256 * 8 + 1: { constexpr int PPT = 1, NT = 256; CALL; } break;            \
+    case 256 * 8 + 2: { constexpr int PPT = 2, NT = 256; CALL; } break;            \
+    case 256 * 8 + 4: { constexpr int PPT = 4, NT = 256; CALL; } break;            \
+    case 512 * 8 + 1: { constexpr int PPT = 1, NT = 512; CALL; } break;            \
+    case 512 * 8 + 2: { constexpr int PPT = 2, NT = 512; CALL; } break;            \
+    case 1024 * 8 + 1: { constexpr int PPT = 1, NT = 1024; CALL; } break;          \
+    default: return PPE_ERR_UNSUPPORTED;                                            \
   }
 
 #define PPE_E_SWITCH(EVAL, CALL)  \
@@ -494,53 +531,69 @@ void finish(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb, int nblk, int
 }
 
 template <typename TS>
-ppe_status_t launch_fft_z(ppe_plan_s* p, const Work<TS>& W, int nb, int dir, int check) {
+ppe_status_t launch_fft_z(ppe_plan_s* p, const Work<TS>& W, int nb, int dir, int check, int kx0, int kx1) {
   const Geom& g = p->g;
-  dim3 grid(g.ny, (g.hx + p->tx - 1) / p->tx, nb);
+  dim3 grid(g.ny, (kx1 - kx0 + p->tx - 1) / p->tx, nb);
   dim3 block(p->tx * p->fz.tc);
   if (dir < 0) {
     PPE_TIMED(p, "k_fft_z_fwd",
               PPE_FFT_SWITCH(p->fz_ct, p->fz, fz,
-                             (k_fft_z<TS, E, -1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check))));
+                             (k_fft_z<TS, E, -1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check, kx0))));
   } else {
     PPE_TIMED(p, "k_fft_z_inv",
               PPE_FFT_SWITCH(p->fz_ct, p->fz, fz,
-                             (k_fft_z<TS, E, +1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check))));
+                             (k_fft_z<TS, E, +1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check, kx0))));
   }
   return PPE_OK;
 }
 
+// The spectral chain: forward z FFT, y tridiagonal solves, inverse z FFT.
+// With spec_chunks > 1 it runs chunk by chunk over the kx range (boundaries
+// on multiples of both the z kernel's and the tridiagonal kernel's kx
+// blocks), so that a chunk of the spectrum can stay in the last-level cache
+// between its three passes.
 template <typename TS>
 ppe_status_t launch_chain(ppe_plan_s* p, const Work<TS>& W, int nb, int check) {
   const Geom& g = p->g;
-  ppe_status_t st = launch_fft_z<TS>(p, W, nb, -1, check);
-  if (st != PPE_OK) return st;
-  dim3 tgrid((g.hx + p->txs - 1) / p->txs, g.nz, nb);
   dim3 tblock(p->txs * p->pch);
   const bool full = g.ny == p->pch * p->mc;
+  const int nbx = (g.hx + p->txs - 1) / p->txs;
   // with refinement (ny > 256 or PPE_FLAG_Y_REFINE) the plain launch skips
   // the blocks holding a system of s < kTriTau or the zero mode, and the
   // refining launch runs just those, one block per list entry
   const unsigned char* skip = p->tri_refine ? p->tri_skip : nullptr;
   const dim3 rgrid(std::max(p->n_rblk, 1), 1, nb);
+  const int unit = std::lcm(p->tx, p->txs);  // kx per chunk step
+  const int units = (g.hx + unit - 1) / unit;
+  const int nch = p->tri_refine ? 1 : std::max(1, std::min(p->spec_chunks, units));
+  for (int c = 0; c < nch; ++c) {
+    const int u0 = (int)((long long)units * c / nch), u1 = (int)((long long)units * (c + 1) / nch);
+    const int kx0 = u0 * unit, kx1 = std::min(g.hx, u1 * unit);
+    const int bx0 = kx0 / p->txs, bx1 = (c == nch - 1) ? nbx : kx1 / p->txs;
+    ppe_status_t st = launch_fft_z<TS>(p, W, nb, -1, check, kx0, kx1);
+    if (st != PPE_OK) return st;
+    const dim3 tgrid(bx1 - bx0, g.nz, nb);
 #define PPE_TRI(MCV, FULLV)                                                                              \
   do {                                                                                                   \
     k_tri<TS, MCV, FULLV, false><<<tgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check,    \
-                                                                         skip, nullptr);                 \
+                                                                         skip, nullptr, bx0, nbx);       \
     if (p->tri_refine && p->n_rblk > 0)                                                                  \
       k_tri<TS, MCV, FULLV, true><<<rgrid, tblock, p->lds_t, p->stream>>>(g, W, p->txs, p->pch, check,   \
-                                                                          nullptr, p->tri_rblk);         \
+                                                                          nullptr, p->tri_rblk, 0, nbx); \
   } while (0)
-  PPE_TIMED(p, "k_tri", {
-    if (p->mc == 4 && full) PPE_TRI(4, true);
-    else if (p->mc == 4) PPE_TRI(4, false);
-    else if (p->mc == 8 && full) PPE_TRI(8, true);
-    else if (p->mc == 8) PPE_TRI(8, false);
-    else if (full) PPE_TRI(16, true);
-    else PPE_TRI(16, false);
-  });
+    PPE_TIMED(p, "k_tri", {
+      if (p->mc == 4 && full) PPE_TRI(4, true);
+      else if (p->mc == 4) PPE_TRI(4, false);
+      else if (p->mc == 8 && full) PPE_TRI(8, true);
+      else if (p->mc == 8) PPE_TRI(8, false);
+      else if (full) PPE_TRI(16, true);
+      else PPE_TRI(16, false);
+    });
 #undef PPE_TRI
-  return launch_fft_z<TS>(p, W, nb, +1, check);
+    st = launch_fft_z<TS>(p, W, nb, +1, check, kx0, kx1);
+    if (st != PPE_OK) return st;
+  }
+  return PPE_OK;
 }
 
 // rho0 = min(rho) on the device for the instances that ask for it (Eq. 27)
@@ -567,8 +620,8 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   dim3 xgrid((unsigned)((npairs + p->rp - 1) / p->rp), 1, nb);
   dim3 xblock(p->rp * p->fx.tc);
   PPE_TIMED(p, "k_rhs",
-            PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT, true><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads, march_lds(p->mrhs, 2),
-                                                        p->stream>>>(tab, g, p->mrhs.m, W))));
+            PPE_MARCH_SWITCH(p->mrhs, (k_rhs<TS, PPT, true, NT><<<dim3(p->mrhs.grid, 1, nb), NT, march_lds(p->mrhs, 2),
+                                                              p->stream>>>(tab, g, p->mrhs.m, W))));
   // the right-hand-side sums are reduced by block 0 of the first row FFT
   PPE_TIMED(p, "k_r2c",
             PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
@@ -614,7 +667,7 @@ ppe_status_t varcoef_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb
   dim3 xgrid((unsigned)((npairs + p->rp - 1) / p->rp), 1, nb);
   dim3 xblock(p->rp * p->fx.tc);
   PPE_TIMED(p, "k_rhs",
-            PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT, false><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads,
+            PPE_MARCH_SWITCH(p->mrhs, (k_rhs<TS, PPT, false, NT><<<dim3(p->mrhs.grid, 1, nb), NT,
                                                                march_lds(p->mrhs, 1), p->stream>>>(tab, g,
                                                                                                    p->mrhs.m, W))));
   finish(p, tab, inst0, nb, p->mrhs.grid, FIN_RHS, 0, tol);
@@ -678,7 +731,7 @@ template <typename TS>
 ppe_status_t defect_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb, double* out) {
   Work<TS> W = make_work<TS>(p, inst0);
   PPE_TIMED(p, "k_rhs",
-            PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<TS, PPT, false><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads,
+            PPE_MARCH_SWITCH(p->mrhs, (k_rhs<TS, PPT, false, NT><<<dim3(p->mrhs.grid, 1, nb), NT,
                                                                march_lds(p->mrhs, 1), p->stream>>>(tab, p->g,
                                                                                                    p->mrhs.m, W))));
   PPE_TIMED(p, "k_resid_var",
@@ -978,7 +1031,7 @@ ppe_status_t ppe_rhs(ppe_plan_t p, const double* rho0, const double* dt, const d
     rho_min_pass(p, tab, i0, nb);
     Work<double> W = make_work<double>(p, i0);
     PPE_TIMED(p, "k_rhs",
-              PPE_PPT_SWITCH(p->mrhs.ppt, (k_rhs<double, PPT, true><<<dim3(p->mrhs.grid, 1, nb), kMarchThreads,
+              PPE_MARCH_SWITCH(p->mrhs, (k_rhs<double, PPT, true, NT><<<dim3(p->mrhs.grid, 1, nb), NT,
                                                                     march_lds(p->mrhs, 2), p->stream>>>(
                                                tab, g, p->mrhs.m, W))));
     finish(p, tab, i0, nb, p->mrhs.grid, FIN_RHS, 0);
@@ -1097,7 +1150,7 @@ ppe_status_t ppe_correct(ppe_plan_t p, const double* rho0, const double* dt, con
       q.dt = dt[i0 + i];
     }
     PPE_TIMED(p, "k_correct",
-              PPE_PPT_SWITCH(p->mcor.ppt, (k_correct<PPT><<<dim3(p->mcor.grid, 1, nb), kMarchThreads,
+              PPE_MARCH_SWITCH(p->mcor, (k_correct<PPT, NT><<<dim3(p->mcor.grid, 1, nb), NT,
                                                             march_lds(p->mcor, 3), p->stream>>>(
                                                tab, g, p->mcor.m, p->partial, p->pstride, i0))));
     finish(p, tab, i0, nb, p->mcor.grid, FIN_CORRECT, 0, tol);
