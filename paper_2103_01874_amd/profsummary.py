@@ -1,11 +1,13 @@
 """Summaries of rocprofv3 databases (rocpd SQLite) for the profiles/ folder.
 
   python -m paper_2103_01874_amd.profsummary trace  DB  --cmd "..."  > profiles/<name>.txt
+  python -m paper_2103_01874_amd.profsummary pmc DB... --title T --cmd "..." > profiles/<name>.txt
   python -m paper_2103_01874_amd.profsummary counters --fetch DB1 --write DB2 --workload W \
          --copy-bytes B --cmd-fetch "..." --cmd-write "..." --out profiles/counters_W.json
 
 `trace` prints per-kernel launch counts and average durations from a
---kernel-trace run.  `counters` turns FETCH_SIZE and WRITE_SIZE (KiB per
+--kernel-trace run.  `pmc` prints the mean per dispatch of every counter of
+one or more --pmc runs, per kernel family.  `counters` turns FETCH_SIZE and WRITE_SIZE (KiB per
 dispatch, from two separate --pmc runs) into HBM bytes per launch, each scaled
 by what the same counter reads for the plain device copy of known size that
 the benchmark runs with --copy-bytes (a 1 GiB read + 1 GiB write elementwise
@@ -103,6 +105,40 @@ def cmd_counters(args):
     print(json.dumps(out, indent=1, sort_keys=True))
 
 
+def cmd_pmc(args):
+    """Mean value per dispatch of every counter in the given --pmc databases,
+    per kernel family, with per-wave figures where SQ_WAVES was collected
+    and byte figures for the TCC request counters (every request of a
+    TCC_EA0_RDREQ_128B count is 128 bytes, TCC_EA0_WRREQ_64B 64 bytes)."""
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in args.db:
+        db = sqlite3.connect(path)
+        for name, cn, v in db.execute("select kernel_name, counter_name, value from counters_collection"):
+            fam = family(name)
+            if fam.startswith("k_"):
+                acc[fam][cn].append(v)
+    print(f"# rocprofv3 counters, mean per dispatch: {args.title}")
+    for cmd in args.cmd:
+        print(f"# command: {cmd}")
+    for fam in sorted(acc):
+        d = {cn: sum(v) / len(v) for cn, v in acc[fam].items()}
+        waves = d.get("SQ_WAVES")
+        parts = []
+        for cn in sorted(d):
+            x = d[cn]
+            if waves and cn.startswith("SQ_INSTS"):
+                parts.append(f"{cn}/wave={x / waves:.1f}")
+            elif cn == "TCC_EA0_RDREQ_128B":
+                parts.append(f"read_bytes={x * 128 / 1e6:.1f}MB")
+            elif cn == "TCC_EA0_WRREQ_64B":
+                parts.append(f"write_bytes={x * 64 / 1e6:.1f}MB")
+            else:
+                parts.append(f"{cn}={x:.6g}")
+        if waves and "SQ_WAIT_INST_ANY" in d and "SQ_WAVE_CYCLES" in d:
+            parts.append(f"wait_inst_frac={d['SQ_WAIT_INST_ANY'] / d['SQ_WAVE_CYCLES']:.3f}")
+        print(f"  {fam}: " + " ".join(parts))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -118,9 +154,15 @@ def main(argv=None):
     c.add_argument("--cmd-fetch", required=True)
     c.add_argument("--cmd-write", required=True)
     c.add_argument("--out", required=True)
+    m = sub.add_parser("pmc")
+    m.add_argument("db", nargs="+")
+    m.add_argument("--title", required=True)
+    m.add_argument("--cmd", action="append", default=[])
     args = ap.parse_args(argv)
     if args.cmd_name == "trace":
         cmd_trace(args)
+    elif args.cmd_name == "pmc":
+        cmd_pmc(args)
     else:
         cmd_counters(args)
 
