@@ -348,16 +348,29 @@ class GpuBackend(Backend):
         if req.source is None or req.inputs is not None:
             return
         torch = self.torch
+        keys = list(req.source.keys())
+        srcs = [req.source[k] for k in keys]
         with torch.cuda.stream(self.stage_stream):
-            req.inputs = {k: v.clone() for k, v in req.source.items()}
+            # one allocation for all the fields and one multi-tensor copy: the
+            # serving loop is a single host thread, so per-field calls would
+            # bound its request rate
+            flat = torch.empty(sum(t.numel() for t in srcs), dtype=srcs[0].dtype, device=srcs[0].device)
+            dsts, off = [], 0
+            for t in srcs:
+                dsts.append(flat[off:off + t.numel()].view(t.shape))
+                off += t.numel()
+            torch._foreach_copy_(dsts, srcs)
             ev = torch.cuda.Event()
             ev.record(self.stage_stream)
+        req.inputs = dict(zip(keys, dsts))
         req.staged = ev
+        req.staged_flat = flat
 
     def release(self, req):
         if req.source is not None:
             req.inputs = None
             req.staged = None
+            req.staged_flat = None
 
     def make_plan(self, slot, shape, batch, lengths, ybc=0):
         nx, ny, nz = shape
@@ -374,8 +387,7 @@ class GpuBackend(Backend):
             ev = getattr(r, "staged", None)
             if ev is not None:
                 st.wait_event(ev)
-                for t in r.inputs.values():  # allocated on the staging stream, used on this one
-                    t.record_stream(st)
+                r.staged_flat.record_stream(st)  # allocated on the staging stream, used on this one
         with torch.cuda.stream(st):
             fields = [r.inputs for r in reqs]
             outs = []

@@ -95,3 +95,33 @@ def test_nonfinite_request_is_isolated():
             assert r.status == 0
             res, rec = alone(r)
             same(r, res)
+
+
+def test_staged_inputs_are_charged_and_equal_alone():
+    """Requests that arrive with a source instead of resident inputs: the
+    backend copies the seven fields into memory of the request's own at
+    admission (charged against the budget with the outputs) and releases it
+    on completion; every result equals the same request solved alone.  A
+    budget that holds two requests' inputs and outputs (and the plans) keeps
+    at most two admitted at a time."""
+    torch = __import__("torch")
+    prs = [synth.mixed_instance(1500 + i, shape=(32, 16, 24)) for i in range(6)]
+    src = [binding.to_device(p) for p in prs]
+    be = GpuBackend(n_slots=2, precision=1, keep_outputs=True)
+    per_req = be.output_bytes((32, 16, 24)) + be.input_bytes((32, 16, 24))
+    budget = 2 * per_req + 4 * be.plan_bytes((32, 16, 24), 2)
+    reqs = []
+    for i, p in enumerate(prs):
+        r = Request(rid=i, shape=(32, 16, 24), inputs=None, source=src[i], rho0=p.rho0, dt=p.dt, arrival=0.0)
+        r.problem = p
+        reqs.append(r)
+    srv = Server(be, budget_bytes=budget, n_slots=2, max_group=2)
+    m = srv.run(reqs, time_limit=60)
+    assert m["served"] == 6 and m["rejected"] == 0
+    assert all(r.inputs is None for r in reqs)  # released
+    assert srv.used == sum(nbytes for _, nbytes in srv.plans.values())
+    for r in reqs:
+        r.inputs = src[r.rid]  # (alone() solves from the source fields)
+        res, rec = alone(r)
+        same(r, res)
+        assert r.info == rec and r.status == 0
