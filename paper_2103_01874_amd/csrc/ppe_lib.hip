@@ -229,8 +229,9 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   // 8 kx columns per block when LDS allows (TX divides the tile: all of an
   // FP64 tile, half of an FP32 one, which measured faster than a full tile)
   p->tx = std::min(1 << g.tws, 8);
-  if (tune_env("PPE_TUNE_TX") > 0) p->tx = std::min(p->tx, tune_env("PPE_TUNE_TX"));
-  while (p->tx > 1 && ((size_t)d.nz * (p->tx + kColPad) * 16 + (size_t)d.nz * 16 > lds_limit || p->tx * tcz > 512))
+  if (tune_env("PPE_TUNE_TX") > 0) p->tx = std::min(1 << g.tws, tune_env("PPE_TUNE_TX"));
+  while (p->tx > 1 && ((size_t)d.nz * (p->tx + kColPad) * 16 + (size_t)d.nz * 16 > lds_limit ||
+                       p->tx * tcz > (p->fz_ct ? 1024 : 512)))
     p->tx /= 2;
   // columns + twiddle table (the plane-sum reduction reuses the column area)
   p->lds_z = std::max((size_t)d.nz * (p->tx + kColPad) * 16, (size_t)p->tx * tcz * 8) + (size_t)d.nz * 16;
@@ -629,7 +630,8 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
   ppe_status_t st = launch_chain<TS>(p, W, nb, 0);
   if (st != PPE_OK) return st;
   PPE_TIMED(p, "k_c2r",
-            PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 0, 0))));
+            PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
+                                   tab, g, fx, W, p->rp, 0, 0))));
   if (mixed) {
     // the refinement residual in the spectrum's precision (the first half of
     // the FP64 residual buffer)
@@ -637,8 +639,8 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
     for (int it = 0; it < p->d.max_refine; ++it) {
       PPE_TIMED(p, "k_resid",
                 PPE_PPT_SWITCH(p->mres.ppt, (k_resid<TS, PPT><<<dim3(p->mres.grid, 1, nb), kMarchThreads,
-                                                                march_lds(p->mres, 1), p->stream>>>(tab, g, p->mres.m, W,
-                                                                                                    rs))));
+                                                                march_lds(p->mres, 1), p->stream>>>(
+                                                 tab, g, p->mres.m, W, rs))));
       finish(p, tab, inst0, nb, p->mres.grid, FIN_RESID, 1);
       PPE_TIMED(p, "k_r2c",
                 PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_r2c<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
@@ -646,7 +648,8 @@ ppe_status_t solve_typed(ppe_plan_s* p, const PtrTable& tab, int inst0, int nb) 
       st = launch_chain<TS>(p, W, nb, 1);
       if (st != PPE_OK) return st;
       PPE_TIMED(p, "k_c2r",
-                PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(tab, g, fx, W, p->rp, 1, 1))));
+                PPE_FFT_SWITCH(p->fx_ct, p->fx, fx, (k_c2r<TS, E><<<xgrid, xblock, p->lds_x, p->stream>>>(
+                                       tab, g, fx, W, p->rp, 1, 1))));
     }
   }
   return hipGetLastError() == hipSuccess ? PPE_OK : PPE_ERR_DEVICE;
@@ -1481,9 +1484,11 @@ ppe_status_t ppe_solve_noalloc(const ppe_desc_t* desc, void* stream, const doubl
   if (need > kScratchBytes) return PPE_ERR_NOMEM;  // larger than the static workspace
   char* base = static_cast<char*>(scratch_on(dev));
   if (!base) return PPE_ERR_DEVICE;
-  void* parts[11];
+  constexpr int kParts = 11;
+  static_assert(sizeof(sz) / sizeof(sz[0]) == kParts, "workspace parts");
+  void* parts[kParts];
   size_t off = 0;
-  for (int i = 0; i < 11; ++i) {
+  for (int i = 0; i < kParts; ++i) {
     parts[i] = base + off;
     off += al(std::max<size_t>(sz[i], 8));
   }
