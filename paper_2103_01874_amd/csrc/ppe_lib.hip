@@ -146,7 +146,7 @@ size_t spec_elem_bytes(const ppe_desc_t* d) {
 // that a tile plane has about `points` interior cells; KC planes per chunk so
 // that an instance gets about 2048 blocks.
 bool march_shape(const ppe_desc_t& d, int points, int max_txt, const char* env, ppe_plan_s::MarchCfg& c,
-                 int nt = kMarchThreads) {
+                 int nt = kMarchThreads, int max_planes = 16) {
   March& M = c.m;
   c.nt = nt;
   if (tune_env("PPE_TUNE_TXT") > 0) max_txt = tune_env("PPE_TUNE_TXT");
@@ -170,7 +170,7 @@ bool march_shape(const ppe_desc_t& d, int points, int max_txt, const char* env, 
   // and at most 16 planes per block: with fewer, longer marches the final
   // set of resident blocks leaves the GPU idle for longer (512x256x512:
   // 128 planes per block, k_correct 1387 us; 16 planes, 1306 us)
-  const int max_planes = tune_env("PPE_TUNE_MAX_PLANES") > 0 ? tune_env("PPE_TUNE_MAX_PLANES") : 16;
+  if (tune_env("PPE_TUNE_MAX_PLANES") > 0) max_planes = tune_env("PPE_TUNE_MAX_PLANES");
   nkc = std::max(nkc, (d.nz + max_planes - 1) / max_planes);
   nkc = std::min(nkc, std::max(1, d.nz / 2));
   M.kc = (d.nz + nkc - 1) / nkc;
@@ -274,15 +274,26 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   if (p->src_vec != 1) p->src_vec = 2;
   // z-marching stencils: TXT x TJ tiles (TXT a divisor of nx, <= 128), KC planes
   // per chunk; the tile height per kernel trades halo traffic against registers
-  // threads per block of the two big stencils (512 and 1024 hold taller
-  // tiles at one point per thread: fewer halo rows fetched per interior row)
+  // On large planes the two big stencils take 64x8 tiles, which fetch fewer
+  // halo rows per interior row than 64x4 where those rows no longer stay in
+  // L2: k_rhs with 512 threads, one point each (planes of >= 16 K cells);
+  // k_correct with 256 threads, two points each (held to four waves per SIMD
+  // by its launch bounds), marching up to 32 planes per block (planes of
+  // >= 64 K cells).  512x256x512 FP64: k_rhs 947 -> 921 us, k_correct
+  // 1284 -> 1241 us, step 3.23 -> 3.14 ms.  On smaller planes the halo rows
+  // hit L2 and the 64x4 tiles keep more waves in flight.
   const auto nt_of = [](const char* env, int def) {
     const int v = tune_env(env);
     return (v == 256 || v == 512 || v == 1024) ? v : def;
   };
-  const int nt_rhs = nt_of("PPE_TUNE_NT_RHS", kMarchThreads), nt_cor = nt_of("PPE_TUNE_NT_COR", kMarchThreads);
-  if (!march_shape(d, nt_rhs == kMarchThreads ? 256 : nt_rhs, 64, "PPE_TUNE_TJ_RHS", p->mrhs, nt_rhs) ||
-      !march_shape(d, nt_cor == kMarchThreads ? 256 : nt_cor, 64, "PPE_TUNE_TJ_COR", p->mcor, nt_cor) ||
+  const long long plane_cells = (long long)d.nx * d.ny;
+  const bool big_rhs = plane_cells >= 16384, big_cor = plane_cells >= 65536;
+  const int nt_rhs = nt_of("PPE_TUNE_NT_RHS", big_rhs ? 512 : kMarchThreads);
+  const int nt_cor = nt_of("PPE_TUNE_NT_COR", kMarchThreads);
+  const int planes_cor =
+      tune_env("PPE_TUNE_MAX_PLANES_COR") > 0 ? tune_env("PPE_TUNE_MAX_PLANES_COR") : (big_cor ? 32 : 16);
+  if (!march_shape(d, big_rhs ? 512 : 256, 64, "PPE_TUNE_TJ_RHS", p->mrhs, nt_rhs) ||
+      !march_shape(d, big_cor ? 512 : 256, 64, "PPE_TUNE_TJ_COR", p->mcor, nt_cor, planes_cor) ||
       !march_shape(d, 256, 64, "PPE_TUNE_TJ_RES", p->mres))
     return false;
   if ((size_t)3 * p->mcor.tslots * 8 > 65536) return false;
