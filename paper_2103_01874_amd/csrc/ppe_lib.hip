@@ -16,6 +16,7 @@
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <utility>
 #include <new>
 #include <string>
 #include <vector>
@@ -1402,6 +1403,9 @@ ppe_status_t ppe_predict(ppe_plan_t p, const ppe_predict_t* in, double* const* u
   if (hipSetDevice(p->device) != hipSuccess) return PPE_ERR_DEVICE;
   const Geom& g = p->g;
   const unsigned blocks = (unsigned)((g.npts + 255) / 256);
+  // LDS tiles need whole 64-column x tiles; PPE_TUNE_PREDICT_GLOBAL=1 keeps
+  // the one-thread-per-face kernels (the same arithmetic on the same values)
+  const bool tiled = tune_env("PPE_TUNE_PREDICT_GLOBAL") == 0 && g.nx % kPredTX == 0;
   for (int i0 = 0; i0 < B; i0 += kMaxLaunch) {
     const int nb = std::min(kMaxLaunch, B - i0);
     PredTable tab;
@@ -1429,6 +1433,21 @@ ppe_status_t ppe_predict(ppe_plan_t p, const ppe_predict_t* in, double* const* u
       t.wp = wp[i0 + i];
       t.rho_mean = q.rho_mean;
       t.dt = q.dt;
+    }
+    if (tiled) {
+      const unsigned ntx = (unsigned)(g.nx / kPredTX);
+      const dim3 gy(ntx * (unsigned)((g.ny + kPredTR - 1) / kPredTR), (unsigned)g.nz, nb);
+      const dim3 gz(ntx * (unsigned)((g.nz + kPredTR - 1) / kPredTR), (unsigned)g.ny, nb);
+      PPE_TIMED(p, "k_predict_u", (k_predict_tile<0><<<gy, kPredTX * kPredTR, 0, p->stream>>>(tab, g)));
+      PPE_TIMED(p, "k_predict_v", {
+        k_predict_tile<1><<<gy, kPredTX * kPredTR, 0, p->stream>>>(tab, g);
+        if (g.ybc == 1) {  // the outflow top face
+          const unsigned tblocks = (unsigned)(((long long)g.nx * g.nz + 255) / 256);
+          k_predict_vtop<<<dim3(tblocks, 1, nb), 256, 0, p->stream>>>(tab, g);
+        }
+      });
+      PPE_TIMED(p, "k_predict_w", (k_predict_tile<2><<<gz, kPredTX * kPredTR, 0, p->stream>>>(tab, g)));
+      continue;
     }
     PPE_TIMED(p, "k_predict_u", (k_predict<0><<<dim3(blocks, 1, nb), 256, 0, p->stream>>>(tab, g)));
     PPE_TIMED(p, "k_predict_v", {

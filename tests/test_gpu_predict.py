@@ -3,7 +3,10 @@
 The increments u^p - u^n are compared (a large u^n would hide errors in the
 update) at 1e-12 relative in the 2-norm and 1e-11 relative to the largest
 increment pointwise; both sides take the SMART and central/upwind decisions
-with the same products in FP64.
+with the same products in FP64.  Grids whose nx is a multiple of 64 run the
+LDS-tiled kernels; those are also compared with the one-thread-per-face
+kernels (PPE_TUNE_PREDICT_GLOBAL=1), which evaluate the same expressions on
+the same values: bitwise.
 """
 import numpy as np
 import pytest
@@ -159,3 +162,30 @@ def test_predict_rejects_small_ny_and_bad_dt():
     with pytest.raises(binding.PPEError):
         plan.predict([d], out, outv, out)
     plan.close()
+
+
+TILED = [(64, 4, 1), (64, 5, 6), (128, 33, 18), (192, 7, 3), (64, 13, 2), (128, 8, 8)]
+
+
+@pytest.mark.parametrize("ybc", [0, 1])
+@pytest.mark.parametrize("shape", TILED)
+def test_tiled_kernels_against_oracle_and_per_face_kernels(shape, ybc, monkeypatch):
+    """Partial y and z tiles (ny, nz not multiples of 4), one to three
+    planes, the smallest ny, x halos wrapping at both ends of a single tile,
+    and the optional fields on every other shape."""
+    g = O.Grid(*shape, 1.1, 0.8, 1.3, ybc=ybc)
+    r = random_inputs(g, 11 * sum(shape) + ybc)
+    if sum(shape) % 2 == 0:
+        rng = np.random.default_rng(sum(shape))
+        r["uv"] = r["u"] + 0.1 * rng.standard_normal(g.shape)
+        r["vv"] = r["v"] + 0.1 * rng.standard_normal(g.vshape)
+        r["wv"] = r["w"] + 0.1 * rng.standard_normal(g.shape)
+        r["fsx"] = rng.standard_normal(g.shape)
+        r["fsy"] = rng.standard_normal(g.vshape)
+        r["fsz"] = rng.standard_normal(g.shape)
+    (tiled,) = gpu_predict(g, [r])
+    check(g, r, tiled, f"tiled {shape} ybc={ybc}")
+    monkeypatch.setenv("PPE_TUNE_PREDICT_GLOBAL", "1")
+    (per_face,) = gpu_predict(g, [r])
+    for name, a, b in zip("uvw", tiled, per_face):
+        assert np.array_equal(a, b), (name, np.abs(a - b).max())
