@@ -1434,19 +1434,33 @@ ppe_status_t ppe_predict(ppe_plan_t p, const ppe_predict_t* in, double* const* u
       t.rho_mean = q.rho_mean;
       t.dt = q.dt;
     }
+    // the viscous-term velocity is the advected one in every instance
+    bool alias = true;
+    for (int i = 0; i < nb; ++i) {
+      const PredPtrs& t = tab.in[i];
+      alias = alias && t.uv == t.u && t.vv == t.v && t.wv == t.w;
+    }
     if (tiled) {
       const unsigned ntx = (unsigned)(g.nx / kPredTX);
       const dim3 gy(ntx * (unsigned)((g.ny + kPredTR - 1) / kPredTR), (unsigned)g.nz, nb);
       const dim3 gz(ntx * (unsigned)((g.nz + kPredTR - 1) / kPredTR), (unsigned)g.ny, nb);
-      PPE_TIMED(p, "k_predict_u", (k_predict_tile<0><<<gy, kPredTX * kPredTR, 0, p->stream>>>(tab, g)));
+      constexpr int nt = kPredTX * kPredTR;
+      PPE_TIMED(p, "k_predict_u", {
+        if (alias) k_predict_tile<0, true><<<gy, nt, 0, p->stream>>>(tab, g);
+        else k_predict_tile<0, false><<<gy, nt, 0, p->stream>>>(tab, g);
+      });
       PPE_TIMED(p, "k_predict_v", {
-        k_predict_tile<1><<<gy, kPredTX * kPredTR, 0, p->stream>>>(tab, g);
+        if (alias) k_predict_tile<1, true><<<gy, nt, 0, p->stream>>>(tab, g);
+        else k_predict_tile<1, false><<<gy, nt, 0, p->stream>>>(tab, g);
         if (g.ybc == 1) {  // the outflow top face
           const unsigned tblocks = (unsigned)(((long long)g.nx * g.nz + 255) / 256);
           k_predict_vtop<<<dim3(tblocks, 1, nb), 256, 0, p->stream>>>(tab, g);
         }
       });
-      PPE_TIMED(p, "k_predict_w", (k_predict_tile<2><<<gz, kPredTX * kPredTR, 0, p->stream>>>(tab, g)));
+      PPE_TIMED(p, "k_predict_w", {
+        if (alias) k_predict_tile<2, true><<<gz, nt, 0, p->stream>>>(tab, g);
+        else k_predict_tile<2, false><<<gz, nt, 0, p->stream>>>(tab, g);
+      });
       continue;
     }
     PPE_TIMED(p, "k_predict_u", (k_predict<0><<<dim3(blocks, 1, nb), 256, 0, p->stream>>>(tab, g)));

@@ -6,7 +6,9 @@ increment pointwise; both sides take the SMART and central/upwind decisions
 with the same products in FP64.  Grids whose nx is a multiple of 64 run the
 LDS-tiled kernels; those are also compared with the one-thread-per-face
 kernels (PPE_TUNE_PREDICT_GLOBAL=1), which evaluate the same expressions on
-the same values: bitwise.
+the same values: to a few units in the last place of the result (the two are
+compiled separately, and the compiler may fuse a product and a sum into one
+FMA in one and not in the other).
 """
 import numpy as np
 import pytest
@@ -188,4 +190,5 @@ def test_tiled_kernels_against_oracle_and_per_face_kernels(shape, ybc, monkeypat
     monkeypatch.setenv("PPE_TUNE_PREDICT_GLOBAL", "1")
     (per_face,) = gpu_predict(g, [r])
     for name, a, b in zip("uvw", tiled, per_face):
-        assert np.array_equal(a, b), (name, np.abs(a - b).max())
+        d = np.abs(a - b).max()
+        assert d <= 4 * np.finfo(np.float64).eps * np.abs(b).max(), (name, d)
