@@ -1440,6 +1440,25 @@ ppe_status_t ppe_predict(ppe_plan_t p, const ppe_predict_t* in, double* const* u
       const PredPtrs& t = tab.in[i];
       alias = alias && t.uv == t.u && t.vv == t.v && t.wv == t.w;
     }
+    if (tiled && alias && tune_env("PPE_TUNE_PREDICT_NO_MARCH") == 0) {
+      const int run = tune_env("PPE_TUNE_PREDICT_RUN") > 0 ? tune_env("PPE_TUNE_PREDICT_RUN") : 16;
+      const unsigned ntx = (unsigned)(g.nx / kPredTX);
+      const unsigned ty = ntx * (unsigned)((g.ny + kPredTR - 1) / kPredTR);
+      const unsigned tz = ntx * (unsigned)((g.nz + kPredTR - 1) / kPredTR);
+      const dim3 gy(ty * (unsigned)((g.nz + run - 1) / run), 1, nb);
+      const dim3 gz(tz * (unsigned)((g.ny + run - 1) / run), 1, nb);
+      constexpr int nt = kPredTX * kPredTR;
+      PPE_TIMED(p, "k_predict_u", (k_predict_march<0><<<gy, nt, 0, p->stream>>>(tab, g, run)));
+      PPE_TIMED(p, "k_predict_v", {
+        k_predict_march<1><<<gy, nt, 0, p->stream>>>(tab, g, run);
+        if (g.ybc == 1) {  // the outflow top face
+          const unsigned tblocks = (unsigned)(((long long)g.nx * g.nz + 255) / 256);
+          k_predict_vtop<<<dim3(tblocks, 1, nb), 256, 0, p->stream>>>(tab, g);
+        }
+      });
+      PPE_TIMED(p, "k_predict_w", (k_predict_march<2><<<gz, nt, 0, p->stream>>>(tab, g, run)));
+      continue;
+    }
     if (tiled) {
       const unsigned ntx = (unsigned)(g.nx / kPredTX);
       const dim3 gy(ntx * (unsigned)((g.ny + kPredTR - 1) / kPredTR), (unsigned)g.nz, nb);

@@ -4,11 +4,12 @@ The increments u^p - u^n are compared (a large u^n would hide errors in the
 update) at 1e-12 relative in the 2-norm and 1e-11 relative to the largest
 increment pointwise; both sides take the SMART and central/upwind decisions
 with the same products in FP64.  Grids whose nx is a multiple of 64 run the
-LDS-tiled kernels; those are also compared with the one-thread-per-face
-kernels (PPE_TUNE_PREDICT_GLOBAL=1), which evaluate the same expressions on
-the same values: to a few units in the last place of the result (the two are
-compiled separately, and the compiler may fuse a product and a sum into one
-FMA in one and not in the other).
+LDS kernels: the slab-marching ones when the viscous-term velocity is the
+advected one, else the one-slab tiles.  Those are also compared with the
+one-thread-per-face kernels (PPE_TUNE_PREDICT_GLOBAL=1), which evaluate the
+same expressions on the same values: to a few units in the last place of the
+result (the kernels are compiled separately, and the compiler may fuse a
+product and a sum into one FMA in one and not in the other).
 """
 import numpy as np
 import pytest
@@ -190,5 +191,22 @@ def test_tiled_kernels_against_oracle_and_per_face_kernels(shape, ybc, monkeypat
     monkeypatch.setenv("PPE_TUNE_PREDICT_GLOBAL", "1")
     (per_face,) = gpu_predict(g, [r])
     for name, a, b in zip("uvw", tiled, per_face):
+        d = np.abs(a - b).max()
+        assert d <= 4 * np.finfo(np.float64).eps * np.abs(b).max(), (name, d)
+
+
+@pytest.mark.parametrize("run", [1, 3, 7])
+@pytest.mark.parametrize("ybc", [0, 1])
+def test_march_run_lengths(run, ybc, monkeypatch):
+    """Marches of 1, 3 and 7 slabs (runs that end mid-grid and a last run
+    that is shorter), each against the oracle and the per-face kernels."""
+    g = O.Grid(64, 13, 12, 1.1, 0.8, 1.3, ybc=ybc)
+    r = random_inputs(g, 500 + run + ybc)
+    monkeypatch.setenv("PPE_TUNE_PREDICT_RUN", str(run))
+    (march,) = gpu_predict(g, [r])
+    check(g, r, march, f"march run={run} ybc={ybc}")
+    monkeypatch.setenv("PPE_TUNE_PREDICT_GLOBAL", "1")
+    (per_face,) = gpu_predict(g, [r])
+    for name, a, b in zip("uvw", march, per_face):
         d = np.abs(a - b).max()
         assert d <= 4 * np.finfo(np.float64).eps * np.abs(b).max(), (name, d)
