@@ -36,6 +36,10 @@ def family(name: str) -> str:
     if n.startswith("k_fft_z"):
         # k_fft_z<TS, E, DIR[, plan]>: DIR = -1 forward, 1 inverse
         return "k_fft_z_fwd" if re.match(r"k_fft_z<[^,]+, *\d+, *-1\b", n) else "k_fft_z_inv"
+    m = re.match(r"k_predict(?:_tile|_march)?<(\d)", n)
+    if m:
+        # k_predict*<COMP, ...>: COMP 0 and 3 u, 1 v, 2 w
+        return "k_predict_" + "uvwu"[int(m.group(1))]
     return re.sub(r"<.*", "", n)
 
 
