@@ -210,3 +210,26 @@ def test_march_run_lengths(run, ybc, monkeypatch):
     for name, a, b in zip("uvw", march, per_face):
         d = np.abs(a - b).max()
         assert d <= 4 * np.finfo(np.float64).eps * np.abs(b).max(), (name, d)
+
+
+@pytest.mark.parametrize("separate_vis", [False, True])
+def test_batched_lds_kernels_equal_alone(separate_vis):
+    """Three instances in one launch of the march (shared viscous velocity)
+    or the one-slab tiles (separate arrays): each equals its own launch
+    bitwise and matches the oracle."""
+    g = O.Grid(64, 9, 12, 1.0, 1.0, 1.0, ybc=1)
+    rng = np.random.default_rng(41)
+    recs = []
+    for s in range(3):
+        r = random_inputs(g, 300 + s)
+        if separate_vis:
+            r["uv"] = r["u"] + 0.1 * rng.standard_normal(g.shape)
+            r["vv"] = r["v"] + 0.1 * rng.standard_normal(g.vshape)
+            r["wv"] = r["w"] + 0.1 * rng.standard_normal(g.shape)
+        recs.append(r)
+    got = gpu_predict(g, recs)
+    for r, gg in zip(recs, got):
+        check(g, r, gg, f"batched separate={separate_vis}")
+        (alone,) = gpu_predict(g, [r])
+        for a, b in zip(alone, gg):
+            assert np.array_equal(a, b)
