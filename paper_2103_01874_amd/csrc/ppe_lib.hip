@@ -281,7 +281,10 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   // k_correct with 256 threads, two points each (held to four waves per SIMD
   // by its launch bounds), marching up to 32 planes per block (planes of
   // >= 64 K cells).  512x256x512 FP64: k_rhs 947 -> 921 us, k_correct
-  // 1284 -> 1241 us, step 3.23 -> 3.14 ms.  On smaller planes the halo rows
+  // 1284 -> 1241 us, step 3.23 -> 3.14 ms.  The residual passes take 64x8
+  // tiles (two points per thread) on the same planes: k_resid of the
+  // FP32-spectrum path 304 -> 273 us at 512x256x512 (at 256x128 planes
+  // k_resid_var ran 60 -> 70 us that way).  On smaller planes the halo rows
   // hit L2 and the 64x4 tiles keep more waves in flight.
   const auto nt_of = [](const char* env, int def) {
     const int v = tune_env(env);
@@ -295,7 +298,7 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
       tune_env("PPE_TUNE_MAX_PLANES_COR") > 0 ? tune_env("PPE_TUNE_MAX_PLANES_COR") : (big_cor ? 32 : 16);
   if (!march_shape(d, big_rhs ? 512 : 256, 64, "PPE_TUNE_TJ_RHS", p->mrhs, nt_rhs) ||
       !march_shape(d, big_cor ? 512 : 256, 64, "PPE_TUNE_TJ_COR", p->mcor, nt_cor, planes_cor) ||
-      !march_shape(d, 256, 64, "PPE_TUNE_TJ_RES", p->mres))
+      !march_shape(d, big_cor ? 512 : 256, 64, "PPE_TUNE_TJ_RES", p->mres))
     return false;
   if ((size_t)3 * p->mcor.tslots * 8 > 65536) return false;
   // per-instance partial-sum stride: the largest grid.x of a reducing kernel
