@@ -1444,27 +1444,35 @@ ppe_status_t ppe_predict(ppe_plan_t p, const ppe_predict_t* in, double* const* u
       alias = alias && t.uv == t.u && t.vv == t.v && t.wv == t.w;
     }
     if (tiled && alias && tune_env("PPE_TUNE_PREDICT_NO_MARCH") == 0) {
-      const int run = tune_env("PPE_TUNE_PREDICT_RUN") > 0 ? tune_env("PPE_TUNE_PREDICT_RUN") : 16;
+      const auto run_of = [](const char* env, int def) {
+        const int v = tune_env(env) > 0 ? tune_env(env) : tune_env("PPE_TUNE_PREDICT_RUN");
+        return v > 0 ? v : def;
+      };
+      // slabs per block: at 256x128x256 the y marches (u, w) ran fastest with
+      // 12 (u/w 281/247 us at 16, 270/239 at 12, 275-287/244-257 at 8-14), the
+      // z march (v) with 16 or 32 (293; 315-351 at 20-24)
+      const int run_u = run_of("PPE_TUNE_PREDICT_RUN_U", 12), run_v = run_of("PPE_TUNE_PREDICT_RUN_V", 16),
+                run_w = run_of("PPE_TUNE_PREDICT_RUN_W", 12);
       const unsigned ntx = (unsigned)(g.nx / kPredTX);
       const unsigned ty = ntx * (unsigned)((g.ny + kPredTR - 1) / kPredTR);
       const unsigned tz = ntx * (unsigned)((g.nz + kPredTR - 1) / kPredTR);
-      const dim3 gy(ty * (unsigned)((g.nz + run - 1) / run), 1, nb);
-      const dim3 gz(tz * (unsigned)((g.ny + run - 1) / run), 1, nb);
+      const auto gy = [&](int run) { return dim3(ty * (unsigned)((g.nz + run - 1) / run), 1, nb); };
+      const auto gz = [&](int run) { return dim3(tz * (unsigned)((g.ny + run - 1) / run), 1, nb); };
       constexpr int nt = kPredTX * kPredTR;
       // u marches through y rows like w (faster than through z planes)
       if (tune_env("PPE_TUNE_PREDICT_U_PLANES") != 0) {
-        PPE_TIMED(p, "k_predict_u", (k_predict_march<0><<<gy, nt, 0, p->stream>>>(tab, g, run)));
+        PPE_TIMED(p, "k_predict_u", (k_predict_march<0><<<gy(run_u), nt, 0, p->stream>>>(tab, g, run_u)));
       } else {
-        PPE_TIMED(p, "k_predict_u", (k_predict_march<3><<<gz, nt, 0, p->stream>>>(tab, g, run)));
+        PPE_TIMED(p, "k_predict_u", (k_predict_march<3><<<gz(run_u), nt, 0, p->stream>>>(tab, g, run_u)));
       }
       PPE_TIMED(p, "k_predict_v", {
-        k_predict_march<1><<<gy, nt, 0, p->stream>>>(tab, g, run);
+        k_predict_march<1><<<gy(run_v), nt, 0, p->stream>>>(tab, g, run_v);
         if (g.ybc == 1) {  // the outflow top face
           const unsigned tblocks = (unsigned)(((long long)g.nx * g.nz + 255) / 256);
           k_predict_vtop<<<dim3(tblocks, 1, nb), 256, 0, p->stream>>>(tab, g);
         }
       });
-      PPE_TIMED(p, "k_predict_w", (k_predict_march<2><<<gz, nt, 0, p->stream>>>(tab, g, run)));
+      PPE_TIMED(p, "k_predict_w", (k_predict_march<2><<<gz(run_w), nt, 0, p->stream>>>(tab, g, run_w)));
       continue;
     }
     if (tiled) {
