@@ -570,6 +570,17 @@ __device__ __forceinline__ void fft_io_post(BufT* buf, int es, int t, bool activ
                                                                                v);
 }
 
+// fft_io_v whose last stage hands all of the thread's outputs to store(v),
+// laid out as for fft_io_post.
+template <int E, int DIR, bool PAD, typename T, int N, typename BufT, typename LoadV, typename StoreV>
+__device__ __forceinline__ void fft_io_v_post(BufT* buf, int es, int t, bool active, const CFft<N>&,
+                                              const double* tw, LoadV loadv, StoreV storev) {
+  static_assert(E == CFft<N>::e, "elements per thread of the plan");
+  cplx<T> v[E];
+  fft_io_ct_stage<E, DIR, PAD, true, true, T, N, 0, BufT, LoadV, StoreV, true>(buf, es, t, active, tw, loadv,
+                                                                              storev, v);
+}
+
 template <typename F>
 struct is_ct_fft : std::false_type {};
 template <int N>

@@ -114,6 +114,25 @@ def test_large_power_of_two_lengths(shape, precision, ybc):
     check(pr, got, rec, oracle_step(pr))
 
 
+# The row transforms pack rows 2q and 2q + 1 into one complex FFT; an odd
+# ny * nz leaves the last pair with one row.  Compile-time plans in one
+# wavefront (16..512), across wavefronts (1024) and run-time plans (12, 96),
+# with the refinement update of p in both precisions' paths.
+ODD_ROWS = [(16, 3, 3), (64, 5, 9), (512, 3, 1), (256, 7, 3), (1024, 3, 3), (96, 5, 3), (12, 5, 9)]
+
+
+@pytest.mark.parametrize("ybc", [0, 1])
+@pytest.mark.parametrize("precision", [binding.PPE_PREC_FP64, binding.PPE_PREC_MIXED])
+@pytest.mark.parametrize("shape", ODD_ROWS)
+def test_odd_row_count(shape, precision, ybc):
+    pr = synth.random_problem(*shape, seed=11 + sum(shape) + ybc, ybc=ybc)
+    tol = 1e-12 if precision == binding.PPE_PREC_FP64 else 1e-13
+    (got,), (rec,) = gpu_step([pr], precision=precision, tol=tol, max_refine=3)
+    if precision == binding.PPE_PREC_MIXED:
+        assert rec["iters"] >= 1  # the update of p ran
+    check(pr, got, rec, oracle_step(pr))
+
+
 LONG_Y = [(8, 2048, 4), (4, 1000, 6), (4, 2047, 4)]
 
 
