@@ -44,6 +44,31 @@ def test_smart_characteristic():
     assert np.allclose(O.smart_face(3 * a + 1, 3 * b + 1, 3 * c + 1), 3 * f + 1, atol=1e-12)
 
 
+def test_interface_faces_follow_the_cell_peclet_number():
+    """Sec. 5.4's interface rule in its quotient form: central differences
+    where the cell Peclet number Pe = |m| h / mu is below 2, first-order
+    upwind otherwise; faces away from the interface take SMART.  Decisions
+    within a relative 1e-9 of Pe = 2 are left out (the oracle compares the
+    product |m| h against 2 mu, which may round the other way there)."""
+    rng = np.random.default_rng(7)
+    n = 20000
+    m = rng.standard_normal(n) * rng.choice([1.0, 10.0, 100.0], n)
+    mu = rng.uniform(0.01, 1.0, n)
+    h = rng.uniform(0.01, 0.2, n)
+    st = rng.standard_normal((6, n))
+    iface = rng.uniform(size=n) < 0.5
+    got = O.ppe_oracle._advected(m, *st, iface, mu, h)
+    pe = np.abs(m) * h / mu
+    keep = np.abs(pe - 2.0) > 1e-9 * 2.0
+    up, ce, dn = np.where(m >= 0, st[0], st[3]), np.where(m >= 0, st[1], st[4]), np.where(m >= 0, st[2], st[5])
+    want = np.where(pe < 2.0, 0.5 * (ce + dn), ce)
+    sel = iface & keep
+    assert sel.sum() > 9000 and 0.2 < np.mean(pe[sel] < 2.0) < 0.8
+    assert np.array_equal(got[sel], want[sel])
+    smart = np.array([_smart1(a, b, c) for a, b, c in zip(up[~iface], ce[~iface], dn[~iface])])
+    assert np.allclose(got[~iface], smart, rtol=0, atol=1e-14)
+
+
 # ---------------------------------------------------------------------------
 # helpers
 # ---------------------------------------------------------------------------
