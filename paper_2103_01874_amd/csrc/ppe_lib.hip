@@ -551,14 +551,20 @@ ppe_status_t launch_fft_z(ppe_plan_s* p, const Work<TS>& W, int nb, int dir, int
   const Geom& g = p->g;
   dim3 grid(g.ny, (kx1 - kx0 + p->tx - 1) / p->tx, nb);
   dim3 block(p->tx * p->fz.tc);
+  // two blocks per 128-byte tile row: pair them on one XCD (the range starts
+  // on a tile; with an odd count the last block is a half tile at hx or the
+  // range ends inside a tile, and that block keeps the plain order)
+  const int pair = (p->tx * 2 == (1 << g.tws) && g.ny % 8 == 0 && kx0 % (2 * p->tx) == 0) ? 1 : 0;
   if (dir < 0) {
     PPE_TIMED(p, "k_fft_z_fwd",
               PPE_FFT_SWITCH(p->fz_ct, p->fz, fz,
-                             (k_fft_z<TS, E, -1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check, kx0))));
+                             (k_fft_z<TS, E, -1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check, kx0,
+                                                                                      pair))));
   } else {
     PPE_TIMED(p, "k_fft_z_inv",
               PPE_FFT_SWITCH(p->fz_ct, p->fz, fz,
-                             (k_fft_z<TS, E, +1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check, kx0))));
+                             (k_fft_z<TS, E, +1><<<grid, block, p->lds_z, p->stream>>>(g, fz, W, p->tx, check, kx0,
+                                                                                      pair))));
   }
   return PPE_OK;
 }
