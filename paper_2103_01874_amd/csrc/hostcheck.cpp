@@ -280,4 +280,10 @@ int hc_tri(int ny, int P, double s, int flags, const double* rhs, double* x) {
   return 0;
 }
 
+// The z transform's paired block order for a gx x gy grid: j[L], by[L] for
+// every linear block index L.
+void hc_fftz_pair_map(int gx, int gy, int* j, int* by) {
+  for (int L = 0; L < gx * gy; ++L) fftz_pair_block((unsigned)L, (unsigned)gx, (unsigned)gy, j[L], by[L]);
+}
+
 }  // extern "C"

@@ -264,6 +264,23 @@ PPE_HD int lslot(int n, int es) {
 // Slots a padded row of n elements occupies.
 PPE_HD int padded_len(int n) { return n + (n >> kRowPadShift) + 1; }
 
+// Block order of the z transform when a 128-byte tile row spans two blocks
+// (FP32 spectra): blocks go to the XCDs round-robin by linear index L, and
+// the two halves (by = 2t, 2t + 1) of tile row (j, t) are given L and L + 8,
+// one XCD, dispatched together.  gx = ny (a multiple of 8) blocks per column,
+// gy columns; with gy odd the last column keeps the plain order.
+PPE_HD void fftz_pair_block(unsigned L, unsigned gx, unsigned gy, int& j, int& by) {
+  const unsigned npair = gy & ~1u, head = gx * npair;
+  if (L < head) {
+    const unsigned q = L >> 3, unit = ((q >> 1) << 3) + (L & 7);
+    j = (int)(unit % gx);
+    by = 2 * (int)(unit / gx) + (int)(q & 1);
+  } else {
+    j = (int)(L - head);
+    by = (int)npair;
+  }
+}
+
 // One Stockham stage, split into its read and write halves.
 //   element n of the transform lives at buf[lslot(n, es)]
 //   butterfly j in [0, n/R): inputs j + r n/R, twiddle exp(DIR 2 pi i r (j mod Ns)/(Ns R)),

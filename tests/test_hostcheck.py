@@ -28,6 +28,7 @@ def hc():
     lib.hc_twiddles.argtypes = [ctypes.c_int, dp]
     lib.hc_fft_ct.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
     lib.hc_ct_plan_check.argtypes = [ctypes.c_int]
+    lib.hc_fftz_pair_map.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip]
     return lib
 
 
@@ -194,3 +195,23 @@ def test_tri_refinement_rejects_the_pinned_system(hc):
     rin = np.zeros(16)
     out = np.zeros(16)
     assert hc.hc_tri_refined(8, 2, 0.0, 1, _p(rin), _p(out)) == -1
+
+
+@pytest.mark.parametrize("gx", [8, 16, 64, 96, 256])
+@pytest.mark.parametrize("gy", [1, 2, 3, 17, 18, 33])
+def test_fftz_pair_order_is_a_permutation_with_paired_halves(hc, gx, gy):
+    """The z transform's FP32 block order visits every (j, by) once, and the
+    two halves of each tile row sit 8 linear indices apart (one XCD)."""
+    n = gx * gy
+    j = np.zeros(n, dtype=np.int32)
+    by = np.zeros(n, dtype=np.int32)
+    hc.hc_fftz_pair_map(gx, gy, j.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                        by.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    assert np.all((j >= 0) & (j < gx) & (by >= 0) & (by < gy))
+    key = by.astype(np.int64) * gx + j
+    assert np.array_equal(np.sort(key), np.arange(n))
+    where = np.empty(n, dtype=np.int64)
+    where[key] = np.arange(n)
+    for t in range(gy // 2):
+        a, b = where[(2 * t) * gx + np.arange(gx)], where[(2 * t + 1) * gx + np.arange(gx)]
+        assert np.array_equal(b, a + 8)
