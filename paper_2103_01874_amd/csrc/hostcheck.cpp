@@ -189,7 +189,8 @@ int hc_fft(int n, int dir, const double* in, double* out) {
   return 0;
 }
 
-// hc_fft through the compile-time plan of a power-of-two n in 16..2048.
+// hc_fft through the compile-time plan of n (a power of two in 16..2048, or
+// 96, 192, 384).
 int hc_fft_ct(int n, int dir, const double* in, double* out) {
   std::vector<double> tw = twiddles(n);
   std::vector<cplx<double>> buf(padded_len(n)), regs((size_t)n);
@@ -208,6 +209,9 @@ int hc_fft_ct(int n, int dir, const double* in, double* out) {
     HC_CT(512)
     HC_CT(1024)
     HC_CT(2048)
+    HC_CT(96)
+    HC_CT(192)
+    HC_CT(384)
     default:
       return -1;
   }
@@ -230,6 +234,9 @@ int hc_ct_plan_check(int n) {
     case 512: return ct_plan_check<512>();
     case 1024: return ct_plan_check<1024>();
     case 2048: return ct_plan_check<2048>();
+    case 96: return ct_plan_check<96>();
+    case 192: return ct_plan_check<192>();
+    case 384: return ct_plan_check<384>();
     default: return -1;
   }
 }

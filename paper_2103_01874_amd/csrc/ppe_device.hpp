@@ -120,14 +120,36 @@ constexpr StageTab pow2_stages(int n) {
   return t;
 }
 
+// n = 3 * 2^a (a >= 2): the host's order, a radix-3 stage, then radix-4
+// stages and a last radix 2 for odd a; 12 elements per thread.
+constexpr StageTab three_pow2_stages(int n) {
+  StageTab t{};
+  int a = ilog2_c(n / 3), ns = 1, s = 0;
+  const auto put = [&](int r) {
+    t.radix[s] = r;
+    t.ns[s] = ns;
+    t.tstep[s] = n / (ns * r);
+    ns *= r;
+    ++s;
+  };
+  put(3);
+  for (; a >= 2; a -= 2) put(4);
+  if (a == 1) put(2);
+  return t;
+}
+
+constexpr bool is_pow2_c(int n) { return n >= 1 && (n & (n - 1)) == 0; }
+
 template <int N>
 struct CFft {
-  static_assert(N >= 2 && (N & (N - 1)) == 0, "power of two");
+  static_assert(N >= 2 && (is_pow2_c(N) || (N % 3 == 0 && N >= 12 && is_pow2_c(N / 3))),
+                "a power of two, or three times a power of two of at least 4");
+  static constexpr bool pow2 = is_pow2_c(N);
   static constexpr int n = N;
-  static constexpr int nst = ilog2_c(N) / 3 + (ilog2_c(N) % 3 ? 1 : 0);
-  static constexpr int e = ilog2_c(N) >= 3 ? 8 : N;  // lcm of the radices
+  static constexpr int nst = pow2 ? ilog2_c(N) / 3 + (ilog2_c(N) % 3 ? 1 : 0) : 1 + (ilog2_c(N / 3) + 1) / 2;
+  static constexpr int e = pow2 ? (ilog2_c(N) >= 3 ? 8 : N) : 12;  // lcm of the radices
   static constexpr int tc = N / e;
-  static constexpr StageTab tab = pow2_stages(N);
+  static constexpr StageTab tab = pow2 ? pow2_stages(N) : three_pow2_stages(N);
   const double* tw;  // as in FftDev
 };
 

@@ -67,7 +67,7 @@ struct ppe_plan_s {
   int tx = 1;            // kx columns per block (z FFT)
   int txs = 1, pch = 1;  // systems per block, chunks per system (tri)
   int mc = 16;           // register rows per chunk (template of k_tri)
-  int fx_ct = 0, fz_ct = 0;  // power-of-two lengths run with compile-time FFT plans (0: run-time plan)
+  int fx_ct = 0, fz_ct = 0;  // lengths with a compile-time FFT plan (0: run-time plan)
   bool tri_refine = false;  // one difference-form refinement step in the y solve
   int spec_chunks = 1;   // kx chunks the spectral chain runs in (see launch_chain)
   int src_pt = 8;        // units per thread of k_source (2, 4 or 8)
@@ -193,7 +193,10 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   const ppe_desc_t& d = p->d;
   if (!fft_factor(d.nx, p->fx) || !fft_factor(d.nz, p->fz)) return false;
   {
-    const auto ct = [](int n) { return (n >= 16 && n <= 2048 && (n & (n - 1)) == 0) ? n : 0; };
+    // compile-time plans: powers of two 16..2048, and 96, 192, 384
+    const auto ct = [](int n) {
+      return ((n >= 16 && n <= 2048 && (n & (n - 1)) == 0) || n == 96 || n == 192 || n == 384) ? n : 0;
+    };
     const bool rt = tune_env("PPE_TUNE_RT_FFT") > 0;  // force the run-time plans
     p->fx_ct = rt ? 0 : ct(d.nx);
     p->fz_ct = rt ? 0 : ct(d.nz);
@@ -232,7 +235,7 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   p->tx = std::min(1 << g.tws, 8);
   if (tune_env("PPE_TUNE_TX") > 0) p->tx = std::min(1 << g.tws, tune_env("PPE_TUNE_TX"));
   while (p->tx > 1 && ((size_t)d.nz * (p->tx + kColPad) * 16 + (size_t)d.nz * 16 > lds_limit ||
-                       p->tx * tcz > (p->fz_ct ? 1024 : 512)))
+                       p->tx * tcz > ((p->fz_ct && (p->fz_ct & (p->fz_ct - 1)) == 0) ? 1024 : 512)))
     p->tx /= 2;
   // columns + twiddle table (the plane-sum reduction reuses the column area)
   p->lds_z = std::max((size_t)d.nz * (p->tx + kColPad) * 16, (size_t)p->tx * tcz * 8) + (size_t)d.nz * 16;
@@ -488,6 +491,9 @@ Work<TS> make_work(ppe_plan_s* p, int inst0) {
     PPE_FFT_CT_CASE(512, HF, FV, CALL)                                              \
     PPE_FFT_CT_CASE(1024, HF, FV, CALL)                                             \
     PPE_FFT_CT_CASE(2048, HF, FV, CALL)                                             \
+    PPE_FFT_CT_CASE(96, HF, FV, CALL)                                               \
+    PPE_FFT_CT_CASE(192, HF, FV, CALL)                                              \
+    PPE_FFT_CT_CASE(384, HF, FV, CALL)                                              \
     default: {                                                                      \
       const FftDev FV = to_dev(HF);                                                 \
       PPE_E_SWITCH(FV.e, CALL);                                                     \
@@ -810,6 +816,9 @@ hipError_t allow_big_lds_t(int bytes) {
   if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<512>::e, CFft<512>>(bytes);
   if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<1024>::e, CFft<1024>>(bytes);
   if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<2048>::e, CFft<2048>>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<96>::e, CFft<96>>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<192>::e, CFft<192>>(bytes);
+  if (e == hipSuccess) e = allow_big_lds_e<TS, CFft<384>::e, CFft<384>>(bytes);
   return e;
 }
 hipError_t allow_big_lds(int bytes) {

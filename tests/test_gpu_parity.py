@@ -94,9 +94,10 @@ def test_fp64_sheet_256x128x256_full_oracle():
 # spans several wavefronts and the mirror half goes through LDS or a second
 # read.  z lengths above 1024 leave the column kernel fewer kx columns per
 # block (4 at 1152..2048), so that a column still fits the LDS of a CU; 1152
-# and 1536 run the run-time plan (radix 3).
+# and 1536 run the run-time plan (radix 3); 96, 192 and 384 run compile-time
+# plans with a radix-3 stage (12 values per thread).
 LARGE_POW2 = [(512, 4, 16), (1024, 2, 16), (2048, 2, 8), (16, 4, 512), (16, 2, 1024), (512, 3, 512),
-              (8, 2, 2048), (8, 3, 1536), (16, 2, 1152)]
+              (8, 2, 2048), (8, 3, 1536), (16, 2, 1152), (384, 4, 12), (12, 4, 384), (192, 3, 96)]
 
 
 @pytest.mark.parametrize("ybc", [0, 1])

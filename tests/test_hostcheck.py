@@ -53,10 +53,11 @@ def test_fft_stages_match_numpy(hc, n):
     assert np.abs(y - n * np.fft.ifft(x)).max() < 1e-14 * np.abs(x).sum() + 1e-15
 
 
-@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048, 96, 192, 384])
 def test_compile_time_plans_equal_the_host_plans(hc, n):
-    """Power-of-two lengths run with compile-time stage tables: the same
-    stages as the host factorisation, and bit for bit the same transform."""
+    """Power-of-two lengths and 96, 192, 384 run with compile-time stage
+    tables: the same stages as the host factorisation, and bit for bit the
+    same transform."""
     assert hc.hc_ct_plan_check(n) == 0
     rng = np.random.default_rng(100 + n)
     x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
