@@ -250,6 +250,10 @@ bool shape_plan(ppe_plan_s* p, size_t lds_limit = 65536) {
   P = std::max(P, 1);
   p->pch = P;
   p->txs = std::max(1, 256 / P);
+  // whole 128-byte kx tiles per block where there is room (P = 6: 40 or 32
+  // systems rather than 42), so that no line of the spectrum is split
+  // between two blocks
+  if (p->txs > (1 << g.tws)) p->txs -= p->txs % (1 << g.tws);
   if (p->txs * P > 256) return false;
   const int mmax = (d.ny + P - 1) / P;
   p->mc = mmax <= 4 ? 4 : (mmax <= 8 ? 8 : 16);
