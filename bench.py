@@ -128,6 +128,8 @@ def algorithmic_bytes(kernel: str, nx: int, ny: int, nz: int, precision: int, mo
         "k_predict_u": pred_in + 8 * N,
         "k_predict_v": pred_in + 8 * Nv,
         "k_predict_w": pred_in + 8 * N,
+        # the three components in one launch
+        "k_predict": 3 * pred_in + 16 * N + 8 * Nv,
     }
     return float(table.get(kernel, 0.0))
 

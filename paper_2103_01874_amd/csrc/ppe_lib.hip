@@ -1484,6 +1484,20 @@ ppe_status_t ppe_predict(ppe_plan_t p, const ppe_predict_t* in, double* const* u
       const auto gy = [&](int run) { return dim3(ty * (unsigned)((g.nz + run - 1) / run), 1, nb); };
       const auto gz = [&](int run) { return dim3(tz * (unsigned)((g.ny + run - 1) / run), 1, nb); };
       constexpr int nt = kPredTX * kPredTR;
+      if (tune_env("PPE_TUNE_PREDICT_U_PLANES") == 0 && tune_env("PPE_TUNE_PREDICT_SEPARATE") == 0) {
+        // the three components in one launch (u and w through y rows, v
+        // through z planes), each block range starting on a multiple of 8
+        const unsigned nu = gz(run_u).x, nv = gy(run_v).x, nw = gz(run_w).x;
+        const unsigned nblk = ((nu + 7u) & ~7u) + ((nv + 7u) & ~7u) + nw;
+        PPE_TIMED(p, "k_predict", {
+          k_predict_march_uvw<<<dim3(nblk, 1, nb), nt, 0, p->stream>>>(tab, g, run_u, run_v, run_w, nu, nv, nw);
+          if (g.ybc == 1) {  // the outflow top face of v
+            const unsigned tblocks = (unsigned)(((long long)g.nx * g.nz + 255) / 256);
+            k_predict_vtop<<<dim3(tblocks, 1, nb), 256, 0, p->stream>>>(tab, g);
+          }
+        });
+        continue;
+      }
       // u marches through y rows like w (faster than through z planes)
       if (tune_env("PPE_TUNE_PREDICT_U_PLANES") != 0) {
         PPE_TIMED(p, "k_predict_u", (k_predict_march<0><<<gy(run_u), nt, 0, p->stream>>>(tab, g, run_u)));

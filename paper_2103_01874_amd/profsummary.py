@@ -36,6 +36,8 @@ def family(name: str) -> str:
     if n.startswith("k_fft_z"):
         # k_fft_z<TS, E, DIR[, plan]>: DIR = -1 forward, 1 inverse
         return "k_fft_z_fwd" if re.match(r"k_fft_z<[^,]+, *\d+, *-1\b", n) else "k_fft_z_inv"
+    if n.startswith("k_predict_march_uvw"):
+        return "k_predict"  # the three components in one launch
     m = re.match(r"k_predict(?:_tile|_march)?<(\d)", n)
     if m:
         # k_predict*<COMP, ...>: COMP 0 and 3 u, 1 v, 2 w

@@ -55,6 +55,7 @@ def test_predictor_components():
     reads = 8 * (N + NV + N + 6 * N)  # u, v, w, rho^n, rho^{n+1}, mu, C, sigma, kappa
     assert ab("k_predict_u") == ab("k_predict_w") == reads + 8 * N
     assert ab("k_predict_v") == reads + 8 * NV
+    assert ab("k_predict") == ab("k_predict_u") + ab("k_predict_v") + ab("k_predict_w")
     extra = 8 * (N + NV + N)          # viscous-term velocities given separately
     assert ab("k_predict_u", ctx={"viscous_separate": True}) == reads + extra + 8 * N
 

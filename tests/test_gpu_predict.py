@@ -233,3 +233,20 @@ def test_batched_lds_kernels_equal_alone(separate_vis):
         (alone,) = gpu_predict(g, [r])
         for a, b in zip(alone, gg):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("ybc", [0, 1])
+@pytest.mark.parametrize("shape", [(64, 13, 12), (128, 33, 18), (192, 7, 3)])
+def test_one_launch_equals_launch_per_component(shape, ybc, monkeypatch):
+    """The three marches in one launch (block ranges padded to whole XCD
+    rounds, counts not multiples of 8 here) against one launch per
+    component: bitwise equal, two instances per launch."""
+    g = O.Grid(*shape, 1.1, 0.8, 1.3, ybc=ybc)
+    recs = [random_inputs(g, 700 + 3 * sum(shape) + s + ybc) for s in range(2)]
+    one = gpu_predict(g, recs)
+    monkeypatch.setenv("PPE_TUNE_PREDICT_SEPARATE", "1")
+    sep = gpu_predict(g, recs)
+    for r, a3, b3 in zip(recs, one, sep):
+        check(g, r, a3, f"one launch {shape} ybc={ybc}")
+        for a, b in zip(a3, b3):
+            assert np.array_equal(a, b)
