@@ -27,6 +27,18 @@ struct cplx {
   T re, im;
 };
 
+// One complex value stored with the non-temporal hint, as a single 2-vector
+// store (the address must be aligned to the whole value, as every spectrum
+// element is).
+template <typename T>
+__device__ __forceinline__ void store_nt(cplx<T>* p, const cplx<T>& y) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 v;
+  v.x = y.re;
+  v.y = y.im;
+  __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+}
+
 template <typename T>
 PPE_HD cplx<T> mk(T r, T i) {
   cplx<T> c;

@@ -113,6 +113,7 @@ struct Work {
   const double* lamx;   // [hx]  lam_x(kx)
   const double* lamz;   // [nz]  lam_z(kz)
   int inst0;            // first instance of this launch in the workspace
+  int nt_rows;          // row transforms store with the non-temporal hint
 };
 
 // Inputs and output of the target-divergence pass (Eq. 26) for one instance.

@@ -443,6 +443,15 @@ Work<TS> make_work(ppe_plan_s* p, int inst0) {
   w.lamx = p->lamx;
   w.lamz = p->lamz;
   w.inst0 = inst0;
+  // Grids whose spectrum exceeds the last-level cache (a chunked chain): the
+  // row transforms' outputs are next read after other passes have gone
+  // through the cache, so they are stored non-temporally (512x256x512:
+  // forward z transform 235 -> 221 us per step behind the forward rows;
+  // k_correct 1186 -> 1166 us behind the inverse rows).  Where the spectrum
+  // fits, the hint made the next pass slower (256x128x256: the forward z
+  // transform 28.8 -> 31.8 us).  PPE_TUNE_NT_ROWS=1 forces it on, 2 off.
+  const int nt = tune_env("PPE_TUNE_NT_ROWS");
+  w.nt_rows = nt == 1 ? 1 : (nt == 2 ? 0 : (p->spec_chunks > 1 ? 1 : 0));
   return w;
 }
 

@@ -204,3 +204,22 @@ def test_chunked_spectral_chain_equals_unchunked(precision, ybc, monkeypatch):
         assert res[chunks][1] == res["1"][1]
     got, rec = res["7"]
     PU.check(pr, got, rec, PU.oracle_step(pr), label=f"chunked {'fp64' if precision == FP64 else 'mixed'} ")
+
+
+@pytest.mark.parametrize("shape", [(256, 16, 12), (256, 7, 3)])
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_nontemporal_row_stores_equal_plain(shape, precision, monkeypatch):
+    """The row transforms' non-temporal stores (on by default only where the
+    spectrum is chunked) forced on and off: a cache hint, so bitwise the same
+    step.  Power-of-two rows take the compile-time row transforms that carry
+    the hint; 7 x 3 rows leave the last row without a partner."""
+    pr = synth.random_problem(*shape, seed=9400 + shape[1], ybc=0)
+    res = {}
+    for nt in ("1", "2"):
+        monkeypatch.setenv("PPE_TUNE_NT_ROWS", nt)
+        res[nt] = (run_single(pr, FP64, 0) if precision == FP64 else run_single(pr, MIXED, 3, tol=1e-13))
+    for k in ("p", "u", "v", "w"):
+        assert np.array_equal(res["1"][0][k], res["2"][0][k]), k
+    assert res["1"][1] == res["2"][1]
+    PU.check(pr, res["1"][0], res["1"][1], PU.oracle_step(pr),
+             label=f"nt rows {'fp64' if precision == FP64 else 'mixed'} ")
